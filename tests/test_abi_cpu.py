@@ -1,0 +1,153 @@
+"""Host-side checks that need no GPU: the library loads and exports every
+declared symbol, validation errors are reported before any device work, and
+the BVH built on the host is well formed."""
+import ctypes as C
+import re
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2012_10357_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2012_10357_amd import build
+        build.build()
+    P.lib()
+    return P
+
+
+def test_exports_every_declared_symbol(P):
+    hdr = open(os.path.join(ROOT, "include", "procray.h")).read()
+    declared = set(re.findall(r"^(?:pr_status|const char\*|uint32_t)\s+(pr_\w+)\(", hdr, re.M))
+    assert declared == set(P.EXPORTS)
+    L = C.CDLL(P.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert P.abi_version() == 1
+    assert P.device_count() >= 0
+
+
+def _scene_arrays(desc):
+    import paper_2012_10357_amd as P
+    return desc
+
+
+def test_invalid_scenes_rejected_before_device(P):
+    good = W.c2_scene()
+    P.Scene(good, build=False).close()
+    bad = W.c2_scene(); bad.geom_type = bad.geom_type.copy(); bad.geom_type[0] = 9
+    with pytest.raises(P.ProcrayError, match="INVALID_ARG"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.inst_geom = bad.inst_geom.copy(); bad.inst_geom[1] = 17
+    with pytest.raises(P.ProcrayError, match="INVALID_ARG"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.inst_xform = bad.inst_xform.copy(); bad.inst_xform[0, :] = 0
+    with pytest.raises(P.ProcrayError, match="det"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.geom_aabb = bad.geom_aabb.copy(); bad.geom_aabb[0, 0] = 5
+    with pytest.raises(P.ProcrayError, match="lo > hi"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.geom_params = bad.geom_params.copy(); bad.geom_params[2, 0] = 7  # power 7
+    with pytest.raises(P.ProcrayError, match="UNSUPPORTED"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.mat_refl = np.array([0.3, 1.5, 0.3], np.float32)
+    with pytest.raises(P.ProcrayError, match="rho"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.geom_params = bad.geom_params.copy(); bad.geom_params[1, 4] = 0
+    with pytest.raises(P.ProcrayError, match="n_iter"):
+        P.Scene(bad, build=False)
+
+
+def test_render_argument_errors_before_device(P):
+    sc = P.Scene(W.c1_scene(), build=False)
+    cam = W.camera((0, 1, -4))
+    o = W.RenderOpts(64, 64, max_steps=128)
+    fake = type("T", (), {"shape": (64, 64, 3), "data_ptr": lambda self: 0})()
+    # not built yet
+    with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
+        P.render(sc, cam, o, fake)
+    sc.build(P.BvhOpts(32, 1, 1.0, 4.0, P.PR_BVH_HOST_ONLY))
+    for bad_cam in (W.camera((0, 0, 0), (0, 0, 0)), W.camera((0, 5, 0), (0, 0, 0), up=(0, 1, 0)),
+                    W.Camera(np.float32([0, 1, -4]), np.float32([0, 0, 0]), np.float32([0, 1, 0]), 180.0)):
+        with pytest.raises(P.ProcrayError, match="INVALID_ARG"):
+            P.render(sc, bad_cam, o, fake)
+    for kw in (dict(spp=0), dict(spp=65), dict(max_steps=0), dict(eps=0.0), dict(tmin=5.0, tmax=1.0),
+               dict(bounces=2)):
+        oo = W.RenderOpts(64, 64, **{**dict(max_steps=128), **kw})
+        with pytest.raises(P.ProcrayError):
+            P.render(sc, cam, oo, fake)
+    big = type("T", (), {"shape": (16385, 4, 3), "data_ptr": lambda self: 0})()
+    with pytest.raises(P.ProcrayError, match="width and height"):
+        P.render(sc, cam, o, big)
+    with pytest.raises(P.ProcrayError, match="tile"):
+        P.render(sc, cam, o, fake, tile=(8, 4))
+    # host-only build: not uploaded, so rendering is refused before any device call
+    with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
+        P.render(sc, cam, o, fake)
+    sc.close()
+
+
+@pytest.mark.parametrize("max_leaf", [1, 4])
+def test_bvh_well_formed_and_culls_like_brute_force(P, max_leaf):
+    desc = W.c3_scene()
+    sc = P.Scene(desc, build=False)
+    sc.build(P.BvhOpts(32, max_leaf, 1.0, 4.0, P.PR_BVH_HOST_ONLY))
+    lo, hi, first, count, order = sc.bvh()
+    n = desc.n_inst
+    assert sorted(order.tolist()) == list(range(n))
+    leaves = np.nonzero(count > 0)[0]
+    assert count[leaves].sum() == n and count.max() <= max_leaf
+    covered = np.zeros(n, int)
+    for l in leaves:
+        covered[first[l]:first[l] + count[l]] += 1
+    assert np.all(covered == 1)
+    # world AABBs of instances from their 8 transformed corners
+    xf = desc.inst_xform.reshape(-1, 3, 4).astype(np.float64)
+    g = desc.geom_aabb[desc.inst_geom].astype(np.float64)
+    corners = np.stack([np.stack([g[:, 0 + 3 * (c & 1)], g[:, 1 + 3 * ((c >> 1) & 1)],
+                                  g[:, 2 + 3 * ((c >> 2) & 1)]], -1) for c in range(8)], 1)
+    wc = np.einsum("kij,kcj->kci", xf[:, :, :3], corners) + xf[:, None, :, 3]
+    wlo, whi = wc.min(1), wc.max(1)
+    # parents contain children, leaves contain their instances
+    def depth(i):
+        return 0 if count[i] else 1 + max(depth(first[i]), depth(first[i] + 1))
+    assert depth(0) <= 30
+    for i in range(len(count)):
+        if count[i] == 0:
+            for c in (first[i], first[i] + 1):
+                assert np.all(lo[i] <= lo[c]) and np.all(hi[i] >= hi[c])
+        else:
+            ids = order[first[i]:first[i] + count[i]]
+            assert np.all(lo[i] <= wlo[ids]) and np.all(hi[i] >= whi[ids])
+    # CPU traversal of the exported BVH == brute-force world-box test on random rays
+    rng = np.random.default_rng(0)
+    o = rng.uniform(-30, 30, (300, 3))
+    d = rng.standard_normal((300, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+
+    def box_hit(o1, d1, l, h):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a = (l - o1) / d1
+            b = (h - o1) / d1
+        return np.max(np.minimum(a, b)) <= max(np.min(np.maximum(a, b)), 0)
+
+    for r in range(300):
+        found = set()
+        stack = [0]
+        while stack:
+            i = stack.pop()
+            if not box_hit(o[r], d[r], lo[i], hi[i]):
+                continue
+            if count[i]:
+                found |= set(order[first[i]:first[i] + count[i]].tolist())
+            else:
+                stack += [first[i], first[i] + 1]
+        brute = {k for k in range(n) if box_hit(o[r], d[r], wlo[k], whi[k])}
+        assert brute <= found
+    sc.close()

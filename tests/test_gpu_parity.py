@@ -1,0 +1,124 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Inputs are the seeded workloads; the oracle runs on the same float32 arrays.
+Full frames where the oracle finishes in seconds (several tiles and ragged
+edges), and seeded pixel samples of the full-size frames rendered in the
+launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tracer as T
+from tests import parity
+from tests.gpu_util import require_gpu, gpu_render, flat
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(rep):
+    print(parity.fmt(rep), flush=True)
+    assert rep["pass"], parity.fmt(rep)
+
+
+def test_c1_full_frame():
+    P = require_gpu()
+    wl = W.c1()
+    scene, req = wl.scenes[0], wl.requests[0]
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, req.camera, req.opts)
+    orc = T.render(scene, req.camera, req.opts)
+    rep = parity.compare(*flat(*g), orc, "c1 64x64")
+    _check(rep)
+    assert rep["mask_all"] >= 0.999
+
+
+@pytest.mark.parametrize("size", [(200, 113), (61, 37)])
+def test_c2_small_full_frame(size):
+    P = require_gpu()
+    wl = W.c2(*size)
+    scene, req = wl.scenes[0], wl.requests[0]
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, req.camera, req.opts)
+    orc = T.render(scene, req.camera, req.opts)
+    _check(parity.compare(*flat(*g), orc, f"c2 {size}"))
+
+
+def test_c2_1080p_sampled():
+    P = require_gpu()
+    wl = W.c2()
+    scene, req = wl.scenes[0], wl.requests[0]
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, req.camera, req.opts)
+    assert np.isfinite(g[0]).all()
+    pix = W.pixel_sample(1920, 1080, 3000, seed=7)
+    # bias the sample toward the objects: half uniform, half inside the hit region
+    hit_pix = np.nonzero(g[2].reshape(-1) >= 0)[0]
+    rng = np.random.default_rng(8)
+    pix = np.unique(np.concatenate([pix, rng.choice(hit_pix, 3000, replace=False)]))
+    orc = T.render(scene, req.camera, req.opts, pixels=pix)
+    _check(parity.compare(*flat(*g, pixels=pix), orc, "c2 1080p sampled"))
+
+
+def test_c3_1080p_4spp_sampled():
+    P = require_gpu()
+    wl = W.c3()
+    scene, req = wl.scenes[0], wl.requests[0]
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, req.camera, req.opts)
+    assert np.isfinite(g[0]).all()
+    pix = W.pixel_sample(1920, 1080, 1500, seed=9)
+    orc = T.render(scene, req.camera, req.opts, pixels=pix)
+    _check(parity.compare(*flat(*g, pixels=pix), orc, "c3 1080p 4spp sampled"))
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (1, 97), (130, 1), (65, 3)])
+def test_degenerate_and_ragged_sizes(wh):
+    P = require_gpu()
+    wl = W.c2(*wh)
+    scene, req = wl.scenes[0], wl.requests[0]
+    # point the camera at the Mandelbulb so tiny images still hit something
+    cam = W.camera((0.9, 0.3, -3.0), (0.9, 0.1, -0.9))
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, req.opts)
+    orc = T.render(scene, cam, req.opts)
+    rep = parity.compare(*flat(*g), orc, f"ragged {wh}")
+    print(parity.fmt(rep))
+    keep = orc["excl"] == 0
+    assert np.array_equal((flat(*g)[2] >= 0)[keep], (orc["inst"] >= 0)[keep])
+
+
+def test_spp_jitter_matches_oracle():
+    P = require_gpu()
+    scene = W.c1_scene()
+    cam = W.camera((0, 1, -4))
+    opts = W.RenderOpts(48, 40, spp=5, jitter=1, seed=(1 << 40) + 12345, max_steps=128, eps=1e-4,
+                        tmax=100.0, shadows=1)
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, opts)
+    orc = T.render(scene, cam, opts)
+    _check(parity.compare(*flat(*g), orc, "c1 5spp jitter"))
+
+
+def test_all_types_scene_with_bounce():
+    """Every primitive type, non-trivial rotations and scales, shadows and a bounce."""
+    P = require_gpu()
+    rng = np.random.default_rng(31)
+    b = W._SceneBuilder()
+    geoms = [W.geom_sphere(1.0), W.geom_box((0.1, 0, 0), (0.6, 0.4, 0.5)), W.geom_torus(1.0, 0.3),
+             W.geom_boxframe(1.0, 0.05), W.geom_pacman(0.8, 60.0),
+             W.geom_julia(rng.uniform(-0.8, 0.8, 4), 12, 4.0), W.geom_mandelbulb(8, 10, 2.0)]
+    for i, gg in enumerate(geoms):
+        gi = b.geometry(gg)
+        mi = b.material(rng.uniform(0.2, 0.9, 3), 0.4)
+        pos = (-4.5 + 1.5 * i, 0.3 * (i % 2), 0.5 * (i % 3))
+        b.instance(gi, mi, W.xform(W.random_rotation(rng), 0.6 + 0.1 * i, pos))
+    gnd = b.geometry(W.geom_box((0, -1.6, 0), (8, 0.1, 8)))
+    b.instance(gnd, b.material((0.7, 0.7, 0.7), 0.2), W.xform(np.eye(3), 1.0, (0, 0, 0)))
+    scene = b.build(light_pos=(3, 6, -4))
+    cam = W.camera((0, 2.0, -8.0), (0, 0, 0.3), vfov_deg=55)
+    opts = W.RenderOpts(160, 72, spp=1, max_steps=256, eps=1e-4, tmax=100.0, shadows=1, bounces=1)
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, opts)
+    orc = T.render(scene, cam, opts)
+    _check(parity.compare(*flat(*g), orc, "all types + bounce"))
