@@ -130,7 +130,7 @@ typedef struct pr_server pr_server;
  * lo <= hi; finite transform with |det A| > 1e-12; parameters in range:
  * radii > 0, 1 <= n_iter <= 64, bailout > 0, Mandelbulb power == 8 (else
  * PR_ERR_UNSUPPORTED); geometry and material indices in bounds; 1 <= n_inst
- * <= 1<<20) and precomputes per-instance records (A^-1, smallest singular
+ * <= 32768, so that BVH node indices fit 16-bit stack entries) and precomputes per-instance records (A^-1, smallest singular
  * value of A, local AABB, parameters, material) on the host.  Touches no
  * device.  The scene is owned by the caller until pr_scene_destroy. */
 pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom,
@@ -241,6 +241,14 @@ typedef struct {
  * ones together on a free stream while earlier launches are still running,
  * and records completion times.  Scenes stay resident on the device. */
 pr_status pr_server_create(const pr_server_opts* opts, pr_server** out);
+/* The same scheduler driven by a simulated device: a launch "completes"
+ * 20 us + us_per_mpix microseconds per million pixel-samples after it
+ * starts, and no device memory is allocated or touched (output pointers
+ * are placeholders that must not be dereferenced).  Meant for host-only
+ * tests of admission, batching and latency accounting; scenes need only a
+ * host BVH (PR_BVH_HOST_ONLY). */
+pr_status pr_server_create_simulated(const pr_server_opts* opts, uint32_t us_per_mpix,
+                                     pr_server** out);
 /* Registers a built scene; the server does not take ownership. */
 pr_status pr_server_add_scene(pr_server* srv, pr_scene* scene, uint32_t* scene_slot);
 /* Queues a request (out_* fields are ignored: the server allocates outputs

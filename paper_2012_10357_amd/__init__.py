@@ -29,7 +29,7 @@ PR_BVH_HOST_ONLY = 1
 EXPORTS = [
     "pr_scene_create", "pr_bvh_build", "pr_scene_bvh_export", "pr_scene_device_bytes",
     "pr_scene_destroy", "pr_render", "pr_render_counts", "pr_render_batch", "pr_autotune",
-    "pr_server_create", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
+    "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
     "pr_abi_version", "pr_device_count",
 ]
@@ -145,6 +145,7 @@ def lib():
         "pr_render_batch": [P, U32, P, P],
         "pr_autotune": [P, U32, P],
         "pr_server_create": [P, C.POINTER(C.c_void_p)],
+        "pr_server_create_simulated": [P, U32, C.POINTER(C.c_void_p)],
         "pr_server_add_scene": [P, P, C.POINTER(U32)],
         "pr_server_submit": [P, P, C.POINTER(U64)],
         "pr_server_wait": [P, U64, U32, P],
@@ -298,6 +299,57 @@ def autotune(reqs) -> BatchOpts:
     best = BatchOpts()
     _check(lib().pr_autotune(reqs, len(reqs), C.byref(best)))
     return best
+
+
+class Server:
+    """Continuous-batching server (pr_server_*).  ``simulated_us_per_mpix``
+    selects the host-only simulated executor."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 2, device: int = 0,
+                 max_batch: int = 256, use_graph: bool = False,
+                 simulated_us_per_mpix: Optional[int] = None):
+        L = lib()
+        o = ServerOpts(hbm_budget_bytes, max_inflight, device, max_batch, 1 if use_graph else 0)
+        h = C.c_void_p()
+        if simulated_us_per_mpix is None:
+            _check(L.pr_server_create(C.byref(o), C.byref(h)))
+        else:
+            _check(L.pr_server_create_simulated(C.byref(o), simulated_us_per_mpix, C.byref(h)))
+        self.handle = h
+
+    def add_scene(self, scene: Scene) -> int:
+        slot = C.c_uint32()
+        _check(lib().pr_server_add_scene(self.handle, scene.handle, C.byref(slot)))
+        return slot.value
+
+    def submit(self, scene: Scene, cam, opts, tag: int = 0) -> int:
+        r = RequestC()
+        r.scene = scene.handle
+        r.cam = camera_c(cam)
+        r.opts = opts_c(opts)
+        r.width, r.height = opts.width, opts.height
+        r.user_tag = tag
+        t = C.c_uint64()
+        _check(lib().pr_server_submit(self.handle, C.byref(r), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = 60000) -> RequestResult:
+        res = RequestResult()
+        _check(lib().pr_server_wait(self.handle, ticket, timeout_ms, C.byref(res)))
+        return res
+
+    def release(self, ticket: int):
+        _check(lib().pr_server_release(self.handle, ticket))
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(lib().pr_server_stats_get(self.handle, C.byref(s)))
+        return s
+
+    def close(self):
+        if self.handle:
+            _check(lib().pr_server_destroy(self.handle))
+            self.handle = None
 
 
 def device_count() -> int:

@@ -36,3 +36,20 @@ def flat(rgb, t, inst, pixels=None):
     if pixels is not None:
         return rgb[pixels], t[pixels], inst[pixels]
     return rgb, t, inst
+
+
+_hip = None
+
+
+def d2h(ptr: int, shape, dtype):
+    """Copies device memory at a raw pointer into a new NumPy array."""
+    import ctypes as C
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    out = np.empty(shape, dtype)
+    rc = _hip.hipMemcpy(out.ctypes.data, C.c_void_p(ptr), out.nbytes, 2)   # device -> host
+    assert rc == 0, f"hipMemcpy failed: {rc}"
+    return out

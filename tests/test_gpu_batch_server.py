@@ -1,0 +1,152 @@
+"""GPU tests of the batched and served forms and of scheduling invariance.
+
+Results must not depend on how work is scheduled: tile shape, step budget,
+BVH build options, batch composition, hipGraph replay or the server's mix
+all give bitwise-identical pixels."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tracer as T
+from tests import parity
+from tests.gpu_util import require_gpu, gpu_render, alloc, flat, d2h
+
+pytestmark = pytest.mark.gpu
+
+
+def _eq(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_tile_and_budget_invariance():
+    P = require_gpu()
+    wl = W.c2(320, 180)
+    sc = P.Scene(wl.scenes[0])
+    req = wl.requests[0]
+    ref = gpu_render(P, sc, req.camera, req.opts)
+    for tile in ((16, 4), (32, 2), (64, 1)):
+        for budget in (1, 5, 64):
+            _eq(ref, gpu_render(P, sc, req.camera, req.opts, tile=tile, step_budget=budget))
+
+
+def test_bvh_option_invariance():
+    P = require_gpu()
+    desc = W.random_instances_scene(np.random.default_rng(3), 300, W.C3_KINDS)
+    cam = W.camera((0, 0, -45))
+    opts = W.RenderOpts(256, 144, spp=2, jitter=1, seed=5, max_steps=256, tmax=200.0)
+    ref = gpu_render(P, P.Scene(desc), cam, opts)
+    for bo in (P.BvhOpts(8, 1, 1.0, 4.0, 0), P.BvhOpts(64, 4, 1.0, 1.0, 0), P.BvhOpts(16, 8, 2.0, 1.0, 0)):
+        _eq(ref, gpu_render(P, P.Scene(desc, bvh=bo), cam, opts))
+
+
+def _c4_small(n=24):
+    wl = W.c4(n_requests=n, lo=64, hi=320)
+    return wl
+
+
+def test_batch_equals_alone_and_graph_replays():
+    P = require_gpu()
+    import torch
+    wl = _c4_small()
+    sc = P.Scene(wl.scenes[0])
+    outs, alone = [], []
+    for r in wl.requests:
+        alone.append(gpu_render(P, sc, r.camera, r.opts))
+        outs.append(alloc(r.opts.width, r.opts.height))
+    reqs = P.make_requests([(sc, r.camera, r.opts, *o, i) for i, (r, o) in enumerate(zip(wl.requests, outs))])
+    P.render_batch(reqs)
+    torch.cuda.synchronize()
+    for o, a in zip(outs, alone):
+        _eq([x.cpu().numpy() for x in o], a)
+    # graph capture + replays, with eager work and synchronisation in between
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        for o in outs:
+            for x in o:
+                x.fill_(-3)
+        with torch.cuda.stream(stream):
+            P.render_batch(reqs, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        for o, a in zip(outs, alone):
+            _eq([x.cpu().numpy() for x in o], a)
+        gpu_render(P, sc, wl.requests[0].camera, wl.requests[0].opts)   # eager work between replays
+
+
+def test_batch_mixed_scenes_and_parity():
+    P = require_gpu()
+    import torch
+    s1 = W.c2_scene()
+    s2 = W.random_instances_scene(np.random.default_rng(4), 200, W.C5_KINDS)
+    sc1, sc2 = P.Scene(s1), P.Scene(s2)
+    items = [(sc1, s1, W.c2_camera(), W.RenderOpts(97, 61, max_steps=256, bounces=1)),
+             (sc2, s2, W.camera((0, 5, -50)), W.RenderOpts(80, 80, spp=3, jitter=1, seed=11, max_steps=256, tmax=200.0)),
+             (sc1, s1, W.camera((3, 2, -4)), W.RenderOpts(64, 48, max_steps=256))]
+    outs = [alloc(o.width, o.height) for _, _, _, o in items]
+    reqs = P.make_requests([(sc, cam, o, *out, i) for i, ((sc, _, cam, o), out) in enumerate(zip(items, outs))])
+    P.render_batch(reqs)
+    torch.cuda.synchronize()
+    for (sc, desc, cam, o), out in zip(items, outs):
+        g = [x.cpu().numpy() for x in out]
+        _eq(g, gpu_render(P, sc, cam, o))
+        rep = parity.compare(*flat(*g), T.render(desc, cam, o), f"batch {o.width}x{o.height}")
+        print(parity.fmt(rep))
+        assert rep["pass"]
+
+
+def test_autotune_returns_valid_choice():
+    P = require_gpu()
+    wl = W.c4(n_requests=4, lo=64, hi=128)
+    sc = P.Scene(wl.scenes[0])
+    outs = [alloc(r.opts.width, r.opts.height) for r in wl.requests]
+    reqs = P.make_requests([(sc, r.camera, r.opts, *o, i) for i, (r, o) in enumerate(zip(wl.requests, outs))])
+    best = P.autotune(reqs)
+    assert best.tile_w * best.tile_h == 64 and best.step_budget >= 1
+
+
+def test_server_mix_equals_alone():
+    P = require_gpu()
+    scenes = [W.c2_scene(), W.random_instances_scene(np.random.default_rng(5), 300, W.C5_KINDS)]
+    dev = [P.Scene(s) for s in scenes]
+    srv = P.Server(256 << 20, max_inflight=3, max_batch=16)
+    for d in dev:
+        srv.add_scene(d)
+    reqs = W.c5_requests(24, lo=64, hi=256, n_scenes=2, seed=77)
+    tickets = []
+    for i, r in enumerate(reqs):
+        if r.scene_index == 0:
+            r.camera = W.camera((1.0 * (i % 3), 1.5, -6.0))
+        tickets.append(srv.submit(dev[r.scene_index], r.camera, r.opts, tag=i))
+    for tk, r in zip(tickets, reqs):
+        res = srv.wait(tk, 60000)
+        H, Wd = res.height, res.width
+        got = (d2h(res.rgb, (H, Wd, 3), np.float32), d2h(res.t, (H, Wd), np.float32),
+               d2h(res.inst, (H, Wd), np.int32))
+        _eq(got, gpu_render(P, dev[r.scene_index], r.camera, r.opts))
+        assert res.t_submit <= res.t_admit <= res.t_launch <= res.t_done
+        srv.release(tk)
+    st = srv.stats()
+    assert st.completed == 24 and st.pool_bytes_in_use == 0
+    srv.close()
+
+
+def test_counts_match_oracle_work():
+    """The instrumented kernel's work counts against the oracle's canonical
+    front-to-back counts on the same frame (BVH order and float32 step
+    sequences differ slightly, so this is a tolerance check)."""
+    P = require_gpu()
+    import torch
+    wl = W.c2(160, 90)
+    scene, req = wl.scenes[0], wl.requests[0]
+    sc = P.Scene(scene)
+    rgb = torch.empty((90, 160, 3), device="cuda")
+    c = P.render_counts(sc, req.camera, req.opts, rgb).astype(np.float64)
+    orc = T.render(scene, req.camera, req.opts)["counts"]
+    print("gpu evals", c[:7], "oracle", orc["evals"])
+    print("gpu rays", c[28:32], "oracle", orc["rays"])
+    assert list(c[28:32]) == [orc["rays"][k] for k in ("primary", "shadow", "bounce", "bounce_shadow")]
+    ev_g, ev_o = c[:7].sum(), float(sum(orc["evals"]))
+    assert abs(ev_g - ev_o) / ev_o < 0.1
+    it_g, it_o = c[7:14].sum(), float(sum(orc["iters"]))
+    assert abs(it_g - it_o) / it_o < 0.1
+    assert np.array_equal(c[14:21], np.array(orc["normal_evals"], np.float64))
