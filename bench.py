@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--budget", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run one plain device copy of 256 MiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -124,6 +126,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
     wl = W.c2()
     scene_desc, req = wl.scenes[0], wl.requests[0]
     Wd, H = req.opts.width, req.opts.height

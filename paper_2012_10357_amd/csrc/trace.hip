@@ -34,7 +34,10 @@ namespace pr {
 
 namespace {
 
-constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_IDLE = 4;
+constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_IDLE = 4,
+                   M_NORMAL_READY = 5;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr uint32_t kLongJob = 192;   // evaluations after which a pixel counts as long-running
 constexpr uint32_t K_PRIMARY = 0, K_SHADOW = 1, K_BOUNCE = 2, K_BSHADOW = 3;
 
 __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
@@ -86,8 +89,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   __shared__ InstDev lds_insts[kLdsInsts];
   __shared__ ReqDev lds_reqs[kLdsReqs];
   __shared__ SceneConstsDev lds_consts;
+  // pooled normal taps: a lane waiting for a normal posts its local hit point
+  // (FP64), step and instance record; one wave-wide pass then evaluates the
+  // six taps of up to ten pending normals, one tap per lane
+  __shared__ double nrm_pt[kWavesPerBlock][3][kWave];
+  __shared__ float nrm_h[kWavesPerBlock][kWave];
+  __shared__ const InstDev* nrm_inst[kWavesPerBlock][kWave];
+  __shared__ float nrm_res[kWavesPerBlock][6][kWave];
+  __shared__ uint8_t nrm_owner[kWavesPerBlock][kWave];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
   const uint32_t total_jobs = queue->total_jobs;
   const uint32_t n_req = queue->n_req;
   const uint32_t n_sn = queue->n_stage_nodes;
@@ -139,8 +151,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   float prm[6];
   float lo_[3], ld_[3];
   float t = 0.f, t1 = 0.f, sigma = 1.f;
-  int steps = 0, nidx = 0;
-  float gx = 0.f, gy = 0.f, gz = 0.f, hl = 0.f;
+  int steps = 0;
+  uint32_t job_evals = 0;   // estimator evaluations of the current pixel job
+  float gx = 0.f, gy = 0.f, gz = 0.f;
 
   // shading stash
   float sh_lam = 0.f, sh_ar = 0.f, sh_ag = 0.f, sh_ab = 0.f;     // current hit
@@ -266,6 +279,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       return;
     }
     has_job = true;
+    job_evals = 0;
     s = 0;
     acc_r = acc_g = acc_b = 0.f;
     out_t = __builtin_inff();
@@ -351,7 +365,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   };
 
   auto start_normal = [&](int slot, float th) {
-    const InstDev& I = *inst_ptr(slot);
+    const InstDev* ip = inst_ptr(slot);
+    const InstDev& I = *ip;
     float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
     float ol0 = I.Ainv[0] * d0 + I.Ainv[1] * d1 + I.Ainv[2] * d2;
     float ol1 = I.Ainv[3] * d0 + I.Ainv[4] * d1 + I.Ainv[5] * d2;
@@ -359,19 +374,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     float dl0 = I.Ainv[0] * ray.dx + I.Ainv[1] * ray.dy + I.Ainv[2] * ray.dz;
     float dl1 = I.Ainv[3] * ray.dx + I.Ainv[4] * ray.dy + I.Ainv[5] * ray.dz;
     float dl2 = I.Ainv[6] * ray.dx + I.Ainv[7] * ray.dy + I.Ainv[8] * ray.dz;
-    lo_[0] = ol0;
-    lo_[1] = ol1;
-    lo_[2] = ol2;
-    ld_[0] = dl0;
-    ld_[1] = dl1;
-    ld_[2] = dl2;
+    const double tt = (double)th;
+    nrm_pt[wv][0][lane] = (double)ol0 + tt * (double)dl0;
+    nrm_pt[wv][1][lane] = (double)ol1 + tt * (double)dl1;
+    nrm_pt[wv][2][lane] = (double)ol2 + tt * (double)dl2;
+    nrm_h[wv][lane] = R->fd_h / I.sigma;
+    nrm_inst[wv][lane] = ip;
     cur_slot = slot;
-    cur_type = I.type;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) prm[i] = I.prm[i];
-    hl = R->fd_h / I.sigma;
-    gx = gy = gz = 0.f;
-    nidx = 0;
     t = th;
     mode = M_NORMAL;
   };
@@ -498,18 +507,68 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 
     // control: advance every lane to its next estimator evaluation
-    while (has_job && mode != M_MARCH && !(mode == M_NORMAL && nidx < 6)) {
-      if (mode == M_TRAVERSE) {
-        traverse();
-      } else if (mode == M_NORMAL) {
-        after_normal();
-      } else if (mode == M_RAYDONE) {
-        if (kind == K_PRIMARY) {
-          // keep the primary direction for the mirror bounce
-          bounce_ray = ray;
+    auto control = [&]() {
+      while (has_job && mode != M_MARCH && mode != M_NORMAL) {
+        if (mode == M_TRAVERSE) {
+          traverse();
+        } else if (mode == M_NORMAL_READY) {
+          after_normal();
+        } else if (mode == M_RAYDONE) {
+          if (kind == K_PRIMARY) {
+            // keep the primary direction for the mirror bounce
+            bounce_ray = ray;
+          }
+          ray_done();
         }
-        ray_done();
       }
+    };
+    control();
+
+    // pooled FP64 normal taps: lane j of a pass evaluates tap (j mod 6) of
+    // the (j div 6)-th waiting lane
+    const unsigned long long want = __ballot(has_job && mode == M_NORMAL);
+    if (want) {
+      if (has_job && mode == M_NORMAL) {
+        const uint32_t rank =
+            (uint32_t)__popcll(want & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        nrm_owner[wv][rank] = (uint8_t)lane;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t n_taps = 6u * (uint32_t)__popcll(want);
+      for (uint32_t base = 0; base < n_taps; base += kWave) {
+        const uint32_t j = base + (uint32_t)lane;
+        if (j < n_taps) {
+          const uint32_t owner = nrm_owner[wv][j / 6];
+          const uint32_t tap = j % 6, ax = tap >> 1;
+          const double h = (tap & 1) ? -(double)nrm_h[wv][owner] : (double)nrm_h[wv][owner];
+          const InstDev* ip = nrm_inst[wv][owner];
+          float kp[6];
+#pragma unroll
+          for (int i = 0; i < 6; ++i) kp[i] = ip->prm[i];
+          const uint32_t ty = ip->type;
+          int iters;
+          const double v = de_eval64(ty, nrm_pt[wv][0][owner] + (ax == 0 ? h : 0.0),
+                                     nrm_pt[wv][1][owner] + (ax == 1 ? h : 0.0),
+                                     nrm_pt[wv][2][owner] + (ax == 2 ? h : 0.0), kp, &iters);
+          nrm_res[wv][tap][owner] = (float)v;
+          if (COUNT) {
+            atomicAdd(&cnt_lds[14 + ty], 1ull);
+            atomicAdd(&cnt_lds[21 + ty], (unsigned long long)iters);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (has_job && mode == M_NORMAL) {
+        gx = nrm_res[wv][0][lane] - nrm_res[wv][1][lane];
+        gy = nrm_res[wv][2][lane] - nrm_res[wv][3][lane];
+        gz = nrm_res[wv][4][lane] - nrm_res[wv][5][lane];
+        mode = M_NORMAL_READY;
+      }
+      control();
     }
 
     const unsigned long long busy = __ballot(has_job);
@@ -517,16 +576,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (__ballot(!exhausted) == 0ull) break;
       continue;
     }
+    // waves holding long-running pixels get issue priority: the slowest
+    // pixel chains bound the frame time
+    if (__ballot(has_job && job_evals > kLongJob)) {
+      __builtin_amdgcn_s_setprio(2);
+    } else {
+      __builtin_amdgcn_s_setprio(0);
+    }
 
     // burst of lock-step estimator evaluations
     for (int it = 0; it < step_budget; ++it) {
-      const bool active = has_job && (mode == M_MARCH || (mode == M_NORMAL && nidx < 6));
-      if (active && mode == M_MARCH) {
+      const bool active = has_job && mode == M_MARCH;
+      if (active) {
         const float qx = lo_[0] + t * ld_[0];
         const float qy = lo_[1] + t * ld_[1];
         const float qz = lo_[2] + t * ld_[2];
         int iters;
         const float de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        ++job_evals;
         if (COUNT) {
           atomicAdd(&cnt_lds[cur_type], 1ull);
           atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
@@ -554,26 +621,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           ++steps;
           if (t > t1 || steps >= (int)max_steps) mode = M_TRAVERSE;
         }
-      } else if (active) {
-        // central-difference tap (FP64): p_l = o' + t d', +-h along one axis
-        const int ax = nidx >> 1;
-        const double h = (nidx & 1) ? -(double)hl : (double)hl;
-        const double bx = (double)lo_[0] + (double)t * (double)ld_[0];
-        const double by = (double)lo_[1] + (double)t * (double)ld_[1];
-        const double bz = (double)lo_[2] + (double)t * (double)ld_[2];
-        int iters;
-        const double de = de_eval64(cur_type, bx + (ax == 0 ? h : 0.0), by + (ax == 1 ? h : 0.0),
-                                    bz + (ax == 2 ? h : 0.0), prm, &iters);
-        if (COUNT) {
-          atomicAdd(&cnt_lds[14 + cur_type], 1ull);
-          atomicAdd(&cnt_lds[21 + cur_type], (unsigned long long)iters);
-        }
-        const float sgn = (float)((nidx & 1) ? -de : de);
-        if (ax == 0) gx += sgn; else if (ax == 1) gy += sgn; else gz += sgn;
-        ++nidx;
       }
-      const int still = __popcll(__ballot(has_job && (mode == M_MARCH ||
-                                                      (mode == M_NORMAL && nidx < 6))));
+      const int still = __popcll(__ballot(has_job && mode == M_MARCH));
       if (still == 0 || 2 * still < __popcll(busy)) break;
     }
   }
