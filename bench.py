@@ -44,7 +44,7 @@ METRIC = "Mrays/s (primary+shadow) 1080p 4-primitive scene; p50/p99 latency serv
 DE_BASE = {0: 7, 1: 19, 2: 10, 3: 50, 4: 18, 5: 12, 6: 10}
 DE_ITER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 0, 5: 19, 6: 52}
 STEP_FLOPS = 8
-NODE_FLOPS = 56        # popped interior/leaf node: slab test + child ordering
+NODE_FLOPS = 50        # visited interior node: two child slab tests + ordering
 CLIP_FLOPS = 60        # candidate: local transform (33) + local slab clip (27)
 RAYGEN_FLOPS = 60      # camera basis + jitter-free direction + normalisation
 SHADE_FLOPS = 70       # normal mapping, light vector, Lambert, secondary-ray setup
@@ -99,6 +99,158 @@ def _oracle_chunk(pix):
     req = wl.requests[0]
     out = T.render(wl.scenes[0], req.camera, req.opts, pixels=pix)
     return {"rays": out["counts"]["rays"]}
+
+
+KERNEL_SOURCES = ["paper_2012_10357_amd/csrc/trace.hip", "paper_2012_10357_amd/csrc/de.h",
+                  "paper_2012_10357_amd/csrc/internal.h"]
+TRAFFIC_PROFILE = "profiles/trace_kernel_teaser_1080p_pmc.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch from the committed counter profile, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("traffic_") or line.startswith("kernel_source_sha256"):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_batched(P, W, torch, dev):
+    """64 requests over the teaser scene: one persistent launch (graph-captured,
+    autotuned) vs one plain pr_render launch per request, same stream."""
+    wl = W.c4()
+    sc = P.Scene(wl.scenes[0])
+    outs = [torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev)
+            for r in wl.requests]
+    rays = 0
+    for r, o in zip(wl.requests, outs):
+        c = P.render_counts(sc, r.camera, r.opts, o)
+        rays += int(c[28:32].sum())
+    reqs = P.make_requests([(sc, r.camera, r.opts, o, None, None, i)
+                            for i, (r, o) in enumerate(zip(wl.requests, outs))])
+    best = P.autotune(reqs)
+    stream = torch.cuda.Stream(device=dev)
+    reps = 5
+
+    def run(fn):
+        with torch.cuda.stream(stream):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def plain():
+        for r, o in zip(wl.requests, outs):
+            P.render(sc, r.camera, r.opts, o, stream=stream)
+
+    def batched():
+        P.render_batch(reqs, tile=(best.tile_w, best.tile_h), step_budget=best.step_budget,
+                       use_graph=True, stream=stream)
+
+    t_plain, t_batch = run(plain), run(batched)
+    sc.close()
+    return {"requests": len(wl.requests), "rays_per_batch": rays,
+            "batched_mrays_s": round(rays / t_batch / 1e6, 2), "batched_ms": round(t_batch * 1e3, 3),
+            "plain_mrays_s": round(rays / t_plain / 1e6, 2), "plain_ms": round(t_plain * 1e3, 3),
+            "speedup": round(t_plain / t_batch, 3),
+            "tuned": {"tile": [best.tile_w, best.tile_h], "step_budget": best.step_budget}}
+
+
+def bench_served(P, W, torch, dev, seconds):
+    """Open-loop Poisson trace at 200 req/s over 8 resident scenes: the
+    continuous-batching server vs FIFO per-request pr_render launches."""
+    import threading
+    scenes = [P.Scene(s) for s in W.c5_scenes()]
+    n_req = max(20, int(200 * seconds))
+    reqs = W.c5_requests(n_req)
+    prim_rays = sum(r.opts.width * r.opts.height * r.opts.spp for r in reqs)
+
+    # --- server
+    srv = P.Server(16 << 30, max_inflight=4, max_batch=64, use_graph=False)
+    for s in scenes:
+        srv.add_scene(s)
+    tickets = [None] * n_req
+    t_base = time.monotonic() + 0.2
+    sub_err = []
+
+    def submitter():
+        try:
+            for i, r in enumerate(reqs):
+                dt = t_base + r.arrival_s - time.monotonic()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(scenes[r.scene_index], r.camera, r.opts, tag=i)
+        except Exception as e:   # surfaced below
+            sub_err.append(e)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = np.zeros(n_req)
+    done_last = 0.0
+    for i in range(n_req):
+        while tickets[i] is None and th.is_alive():
+            time.sleep(0.0005)
+        if tickets[i] is None:
+            break
+        res = srv.wait(tickets[i], 600000)
+        lat[i] = res.t_done - (t_base + reqs[i].arrival_s)
+        done_last = max(done_last, res.t_done)
+        srv.release(tickets[i])
+    th.join()
+    if sub_err:
+        raise sub_err[0]
+    stats = srv.stats()
+    srv.close()
+    span = done_last - t_base
+    served = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+              "primary_mrays_s": round(prim_rays / span / 1e6, 2), "launches": int(stats.launches)}
+
+    # --- FIFO baseline: one pr_render per request in arrival order, synchronised
+    stream = torch.cuda.Stream(device=dev)
+    lat_f = np.zeros(n_req)
+    buf = {}
+    t_base = time.monotonic() + 0.2
+    with torch.cuda.stream(stream):
+        for i, r in enumerate(reqs):
+            dt = t_base + r.arrival_s - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+            key = (r.opts.height, r.opts.width)
+            if key not in buf:
+                buf[key] = torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev)
+            P.render(scenes[r.scene_index], r.camera, r.opts, buf[key], stream=stream)
+            stream.synchronize()
+            lat_f[i] = time.monotonic() - (t_base + r.arrival_s)
+    span_f = time.monotonic() - t_base
+    for s in scenes:
+        s.close()
+    fifo = {"p50_ms": round(float(np.percentile(lat_f, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat_f, 99)) * 1e3, 2),
+            "primary_mrays_s": round(prim_rays / span_f / 1e6, 2)}
+    return {"requests": n_req, "rate_hz": 200, "trace_s": round(reqs[-1].arrival_s, 2),
+            "server": served, "fifo_plain": fifo}
 
 
 def main():
@@ -181,9 +333,17 @@ def main():
     }
     print(f"# frame: {rays_per_frame} rays, {flops_per_frame / 1e9:.2f} GFLOP, "
           f"kernel {kern_ms:.3f} ms (min {per_launch_ms.min():.3f})", file=sys.stderr, flush=True)
+    traffic = committed_traffic()
+    out["roofline"]["traffic"] = traffic
+    sc.close()
+    if not args.no_batch:
+        out["batched"] = bench_batched(P, W, torch, dev)
+        print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)
+    if not args.no_served:
+        out["served"] = bench_served(P, W, torch, dev, args.served_seconds)
+        print(f"# served: {out['served']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-    sc.close()
     print(json.dumps(out), flush=True)
 
 

@@ -130,8 +130,9 @@ typedef struct pr_server pr_server;
  * lo <= hi; finite transform with |det A| > 1e-12; parameters in range:
  * radii > 0, 1 <= n_iter <= 64, bailout > 0, Mandelbulb power == 8 (else
  * PR_ERR_UNSUPPORTED); geometry and material indices in bounds; 1 <= n_inst
- * <= 32768, so that BVH node indices fit 16-bit stack entries) and precomputes per-instance records (A^-1, smallest singular
- * value of A, local AABB, parameters, material) on the host.  Touches no
+ * <= 16384, so that BVH stack entries fit 16 bits) and precomputes
+ * per-instance records (A^-1, smallest singular value of A, local AABB,
+ * parameters, material) on the host.  Touches no
  * device.  The scene is owned by the caller until pr_scene_destroy. */
 pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom,
                           const pr_instance* insts, uint32_t n_inst,

@@ -44,7 +44,8 @@ void release_ctx(LaunchCtx* c);
 struct pr_scene {
   std::vector<pr::InstDev> host_insts;   // user order
   std::vector<float> world_aabb;         // 6 per instance
-  std::vector<pr::NodeDev> nodes;        // BVH, children adjacent, breadth-first
+  std::vector<pr::HostNode> nodes;       // BVH, children adjacent, breadth-first
+  std::vector<pr::NodeDev> dnodes;       // device layout: child boxes in the parent
   std::vector<uint32_t> order;           // leaf slot -> user instance index
   pr::SceneConstsDev consts{};
   bool built = false;

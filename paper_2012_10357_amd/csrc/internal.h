@@ -30,14 +30,32 @@ struct alignas(16) InstDev {
 };
 static_assert(sizeof(InstDev) == 128, "instance record must stay 128 bytes");
 
-struct alignas(16) NodeDev {
+// Host-side BVH node (the exported layout): children adjacent.
+struct alignas(16) HostNode {
   float lo[3];
   uint32_t first;    // interior: left child index (right = first + 1); leaf: first instance slot
   float hi[3];
   uint32_t count;    // 0 = interior
 };
-static_assert(sizeof(NodeDev) == 32, "BVH node must stay 32 bytes");
-static_assert(sizeof(NodeDev) == sizeof(pr_bvh_node), "exported node layout");
+static_assert(sizeof(HostNode) == 32, "host BVH node must stay 32 bytes");
+static_assert(sizeof(HostNode) == sizeof(pr_bvh_node), "exported node layout");
+
+// Device BVH node: an interior node holding both children's boxes, so one
+// 64-byte load per visited node gives everything needed to test and order
+// its children.  Child k: n == 0 -> interior node c; n >= 1 -> leaf over
+// instance slots [c, c + n); n == kNoChild -> absent (single-leaf scenes).
+constexpr uint32_t kNoChild = 0xffffffffu;
+struct alignas(16) NodeDev {
+  float lo0[3];
+  uint32_t c0;
+  float hi0[3];
+  uint32_t n0;
+  float lo1[3];
+  uint32_t c1;
+  float hi1[3];
+  uint32_t n1;
+};
+static_assert(sizeof(NodeDev) == 64, "device BVH node must stay 64 bytes");
 
 struct alignas(16) SceneConstsDev {
   float light[3];
@@ -92,7 +110,7 @@ struct alignas(16) QueueDev {
 };
 static_assert(sizeof(QueueDev) == 64, "queue header");
 
-constexpr uint32_t kLdsNodes = 256;   // 8 KB: the top eight BVH levels (breadth-first layout)
+constexpr uint32_t kLdsNodes = 128;   // 8 KB: the top seven BVH levels (breadth-first layout)
 constexpr uint32_t kLdsInsts = 64;    // 8 KB of instance records
 constexpr uint32_t kLdsReqs = 8;      // request records staged per workgroup
 

@@ -266,7 +266,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   if (shared) {
     // one scene for the whole launch: every workgroup stages its top BVH
     // levels, first instance records and constants in LDS
-    q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->nodes.size(), kLdsNodes);
+    q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->dnodes.size(), kLdsNodes);
     q.n_stage_insts = std::min<uint32_t>(scenes[0]->consts.n_inst, kLdsInsts);
     q.stage_nodes = scenes[0]->d_nodes;
     q.stage_insts = scenes[0]->d_insts;

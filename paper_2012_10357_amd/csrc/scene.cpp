@@ -49,7 +49,7 @@ pr_status hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-constexpr uint32_t kMaxInstances = 32768;   // BVH node indices fit 16-bit LDS stack entries
+constexpr uint32_t kMaxInstances = 16384;   // BVH stack entries (node, child) fit 16 bits
 constexpr int kMaxDepth = 30;               // traversal stack holds depth + 2 entries
 
 bool finite3(const float* v, int n) {
@@ -220,9 +220,9 @@ void build_bvh(pr_scene* s, const pr_bvh_opts& o) {
   }
   std::vector<uint32_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0u);
-  std::vector<NodeDev> nodes;
+  std::vector<HostNode> nodes;
   nodes.reserve(2 * n);
-  nodes.push_back(NodeDev{});
+  nodes.push_back(HostNode{});
   std::deque<BuildItem> work;   // breadth-first: top levels get the lowest indices
   work.push_back({0, 0, n, 0});
   const uint32_t bins = o.sah_bins;
@@ -323,8 +323,8 @@ void build_bvh(pr_scene* s, const pr_bvh_opts& o) {
     }
     if (mid == it.begin || mid == it.end) mid = it.begin + cnt / 2;
     const uint32_t left = (uint32_t)nodes.size();
-    nodes.push_back(NodeDev{});
-    nodes.push_back(NodeDev{});
+    nodes.push_back(HostNode{});
+    nodes.push_back(HostNode{});
     nodes[it.node].first = left;
     nodes[it.node].count = 0;
     work.push_back({left, it.begin, mid, it.depth + 1});
@@ -332,9 +332,49 @@ void build_bvh(pr_scene* s, const pr_bvh_opts& o) {
   }
   s->nodes = std::move(nodes);
   s->order = std::move(idx);
+  // device layout: one record per interior node (breadth-first order kept),
+  // each holding both children's boxes and references
+  const std::vector<HostNode>& hn = s->nodes;
+  std::vector<uint32_t> dev_index(hn.size(), kNoChild);
+  uint32_t n_int = 0;
+  for (size_t i = 0; i < hn.size(); ++i)
+    if (hn[i].count == 0) dev_index[i] = n_int++;
+  std::vector<NodeDev> dn(std::max<uint32_t>(n_int, 1));
+  auto fill_child = [&](float* lo, float* hi, uint32_t& c, uint32_t& cnt, uint32_t h) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = hn[h].lo[a];
+      hi[a] = hn[h].hi[a];
+    }
+    if (hn[h].count == 0) {
+      c = dev_index[h];
+      cnt = 0;
+    } else {
+      c = hn[h].first;
+      cnt = hn[h].count;
+    }
+  };
+  if (n_int == 0) {
+    // a single leaf: the root record has that leaf as its only child
+    NodeDev& d = dn[0];
+    fill_child(d.lo0, d.hi0, d.c0, d.n0, 0);
+    for (int a = 0; a < 3; ++a) {
+      d.lo1[a] = 0.f;
+      d.hi1[a] = 0.f;
+    }
+    d.c1 = 0;
+    d.n1 = kNoChild;
+  } else {
+    for (size_t i = 0; i < hn.size(); ++i) {
+      if (hn[i].count != 0) continue;
+      NodeDev& d = dn[dev_index[i]];
+      fill_child(d.lo0, d.hi0, d.c0, d.n0, hn[i].first);
+      fill_child(d.lo1, d.hi1, d.c1, d.n1, hn[i].first + 1);
+    }
+  }
+  s->dnodes = std::move(dn);
 }
 
-int bvh_depth(const std::vector<NodeDev>& nodes, uint32_t ni) {
+int bvh_depth(const std::vector<HostNode>& nodes, uint32_t ni) {
   if (nodes[ni].count > 0) return 0;
   return 1 + std::max(bvh_depth(nodes, nodes[ni].first), bvh_depth(nodes, nodes[ni].first + 1));
 }
@@ -482,7 +522,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
     build_bvh(s, o);
     if (bvh_depth(s->nodes, 0) > kMaxDepth)
       return set_error(PR_ERR_UNSUPPORTED, "BVH deeper than %d levels", kMaxDepth);
-    s->consts.n_nodes = (uint32_t)s->nodes.size();
+    s->consts.n_nodes = (uint32_t)s->dnodes.size();
     s->built = true;
     if (o.flags & PR_BVH_HOST_ONLY) return ok();
     free_device(s);
@@ -491,7 +531,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::vector<InstDev> leaf(s->order.size());
     for (size_t k = 0; k < s->order.size(); ++k) leaf[k] = s->host_insts[s->order[k]];
-    const size_t bi = leaf.size() * sizeof(InstDev), bn = s->nodes.size() * sizeof(NodeDev);
+    const size_t bi = leaf.size() * sizeof(InstDev), bn = s->dnodes.size() * sizeof(NodeDev);
     if ((e = hipMalloc((void**)&s->d_insts, bi)) != hipSuccess) return hip_fail(e, "hipMalloc(instances)");
     if ((e = hipMalloc((void**)&s->d_nodes, bn)) != hipSuccess) {
       free_device(s);
@@ -502,7 +542,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
       return hip_fail(e, "hipMalloc(consts)");
     }
     if ((e = hipMemcpy(s->d_insts, leaf.data(), bi, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s->d_nodes, s->nodes.data(), bn, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->d_nodes, s->dnodes.data(), bn, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(s->d_consts, &s->consts, sizeof(SceneConstsDev), hipMemcpyHostToDevice)) !=
             hipSuccess) {
       free_device(s);
@@ -532,7 +572,7 @@ pr_status pr_scene_bvh_export(const pr_scene* s, pr_bvh_node* nodes, uint32_t no
   if (n_order) *n_order = (uint32_t)s->order.size();
   if (nodes) {
     if (node_cap < s->nodes.size()) return set_error(PR_ERR_INVALID_ARG, "node_cap too small");
-    std::memcpy(nodes, s->nodes.data(), s->nodes.size() * sizeof(NodeDev));
+    std::memcpy(nodes, s->nodes.data(), s->nodes.size() * sizeof(HostNode));
   }
   if (order) {
     if (order_cap < s->order.size()) return set_error(PR_ERR_INVALID_ARG, "order_cap too small");

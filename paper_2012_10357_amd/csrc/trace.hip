@@ -38,6 +38,7 @@ constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_I
                    M_NORMAL_READY = 5;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kLongJob = 192;   // evaluations after which a pixel counts as long-running
+constexpr uint32_t kChunk = 64;      // jobs a wave reserves per queue atomic (>= the 64 lanes)
 constexpr uint32_t K_PRIMARY = 0, K_SHADOW = 1, K_BOUNCE = 2, K_BSHADOW = 3;
 
 __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   {
     const uint4* src = (const uint4*)staged_nodes_src;
     uint4* dst = (uint4*)lds_nodes;
-    for (uint32_t i = tid; i < n_sn * 2; i += kBlock) dst[i] = src[i];
+    for (uint32_t i = tid; i < n_sn * 4; i += kBlock) dst[i] = src[i];
     src = (const uint4*)staged_insts_src;
     dst = (uint4*)lds_insts;
     for (uint32_t i = tid; i < n_si * 8; i += kBlock) dst[i] = src[i];
@@ -178,6 +179,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   float eps = 1e-4f;
 
   unsigned long long c_nodes = 0, c_clips = 0;
+  uint32_t res_cur = 0, res_end = 0;   // this wave's reservation of job indices (wave-uniform)
 
   auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) {
     ray = r;
@@ -316,11 +318,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     return true;
   };
 
-  // traversal until a candidate is being marched or the ray is finished
+  // traversal until a candidate is being marched or the ray is finished.
+  // Stack entries (16 bit): an interior node index, or 0x8000 | node << 1 |
+  // child for a leaf child whose candidates are deferred (the far child).
   auto traverse = [&]() {
     const float ix = 1.0f / (ray.dx != 0.f ? ray.dx : copysignf(1e-30f, ray.dx));
     const float iy = 1.0f / (ray.dy != 0.f ? ray.dy : copysignf(1e-30f, ray.dy));
     const float iz = 1.0f / (ray.dz != 0.f ? ray.dz : copysignf(1e-30f, ray.dz));
+    auto box_entry = [&](const float* lo, const float* hi) -> float {
+      float tx0 = (lo[0] - ray.ox) * ix, tx1 = (hi[0] - ray.ox) * ix;
+      float ty0 = (lo[1] - ray.oy) * iy, ty1 = (hi[1] - ray.oy) * iy;
+      float tz0 = (lo[2] - ray.oz) * iz, tz1 = (hi[2] - ray.oz) * iz;
+      float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+      float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
+      return tn <= tf ? tn : __builtin_inff();
+    };
     for (;;) {
       while (leaf_i < leaf_n) {
         int slot = leaf_i++;
@@ -330,36 +342,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         mode = M_RAYDONE;
         return;
       }
-      uint32_t ni = stack_mem[--sp][tid];
-      const NodeDev nd = *node_ptr(ni);
-      if (COUNT) ++c_nodes;
-      float tx0 = (nd.lo[0] - ray.ox) * ix, tx1 = (nd.hi[0] - ray.ox) * ix;
-      float ty0 = (nd.lo[1] - ray.oy) * iy, ty1 = (nd.hi[1] - ray.oy) * iy;
-      float tz0 = (nd.lo[2] - ray.oz) * iz, tz1 = (nd.hi[2] - ray.oz) * iz;
-      float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-      float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
-      if (tn > tf) continue;
-      if (nd.count > 0) {
-        leaf_i = (int)nd.first;
-        leaf_n = (int)(nd.first + nd.count);
+      const uint32_t e = stack_mem[--sp][tid];
+      if (e & 0x8000u) {
+        // deferred leaf child: read its range from the parent record
+        const NodeDev* pn = node_ptr((e & 0x7fffu) >> 1);
+        const uint32_t c = (e & 1u) ? pn->c1 : pn->c0;
+        const uint32_t n = (e & 1u) ? pn->n1 : pn->n0;
+        leaf_i = (int)c;
+        leaf_n = (int)(c + n);
         continue;
       }
-      // interior: visit the nearer child first
-      const uint32_t c0 = nd.first, c1 = nd.first + 1;
-      const NodeDev& A = *node_ptr(c0);
-      const NodeDev& B = *node_ptr(c1);
-      float ea = fmaxf(fmaxf(fminf((A.lo[0] - ray.ox) * ix, (A.hi[0] - ray.ox) * ix),
-                             fminf((A.lo[1] - ray.oy) * iy, (A.hi[1] - ray.oy) * iy)),
-                       fminf((A.lo[2] - ray.oz) * iz, (A.hi[2] - ray.oz) * iz));
-      float eb = fmaxf(fmaxf(fminf((B.lo[0] - ray.ox) * ix, (B.hi[0] - ray.ox) * ix),
-                             fminf((B.lo[1] - ray.oy) * iy, (B.hi[1] - ray.oy) * iy)),
-                       fminf((B.lo[2] - ray.oz) * iz, (B.hi[2] - ray.oz) * iz));
-      if (ea <= eb) {
-        stack_mem[sp++][tid] = (uint16_t)c1;
-        stack_mem[sp++][tid] = (uint16_t)c0;
+      const NodeDev nd = *node_ptr(e);
+      if (COUNT) ++c_nodes;
+      const float t0 = box_entry(nd.lo0, nd.hi0);
+      const float t1c = (nd.n1 != kNoChild) ? box_entry(nd.lo1, nd.hi1) : __builtin_inff();
+      const bool h0 = t0 != __builtin_inff(), h1 = t1c != __builtin_inff();
+      if (!h0 && !h1) continue;
+      // near child first; the far one (if hit) goes on the stack
+      const bool near0 = h0 && (!h1 || t0 <= t1c);
+      if (h0 && h1) {
+        const uint32_t fc = near0 ? nd.c1 : nd.c0, fn = near0 ? nd.n1 : nd.n0;
+        stack_mem[sp++][tid] = (uint16_t)(fn == 0 ? fc : (0x8000u | (e << 1) | (near0 ? 1u : 0u)));
+      }
+      const uint32_t nc = near0 ? nd.c0 : nd.c1, nn = near0 ? nd.n0 : nd.n1;
+      if (nn == 0) {
+        stack_mem[sp++][tid] = (uint16_t)nc;
       } else {
-        stack_mem[sp++][tid] = (uint16_t)c0;
-        stack_mem[sp++][tid] = (uint16_t)c1;
+        leaf_i = (int)nc;
+        leaf_n = (int)(nc + nn);
       }
     }
   };
@@ -486,23 +496,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
   // ---------------- main loop
   for (;;) {
-    // refill idle lanes from the queue (one atomic per wave)
+    // Refill idle lanes.  Each wave holds a reservation of consecutive job
+    // indices [res_cur, res_end) and takes a fresh chunk of kChunk jobs with
+    // one atomic only when the reservation cannot serve all idle lanes; jobs
+    // are handed out in increasing order, so once a lane draws an index past
+    // the end, every index still reserved is past the end too.
     const unsigned long long need = __ballot(!has_job && !exhausted);
     if (need) {
       const int leader = __ffsll((long long)need) - 1;
       const uint32_t n = (uint32_t)__popcll(need);
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&queue->next_job, n);
-      base = __shfl(base, leader);
+      const uint32_t have = res_end - res_cur;
+      uint32_t nbase = 0;
+      if (have < n) {
+        if (lane == leader) nbase = atomicAdd(&queue->next_job, kChunk);
+        nbase = __shfl(nbase, leader);
+      }
       if (!has_job && !exhausted) {
         const uint32_t rank =
             (uint32_t)__popcll(need & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-        const uint32_t j = base + rank;
+        const uint32_t j = rank < have ? res_cur + rank : nbase + (rank - have);
         if (j < total_jobs) {
           start_job(j);
         } else {
           exhausted = true;
         }
+      }
+      if (have < n) {
+        res_cur = nbase + (n - have);
+        res_end = nbase + kChunk;
+      } else {
+        res_cur += n;
       }
     }
 
