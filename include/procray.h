@@ -170,7 +170,12 @@ pr_status pr_scene_destroy(pr_scene* scene);
  *  out_inst  device, width*height int32, instance index hit by the primary
  *            ray of sample 0, -1 on a miss (nullable)
  * Output buffers are owned by the caller and must stay alive until the
- * stream has finished.  1 <= width, height <= 16384. */
+ * stream has finished.  1 <= width, height <= 16384.
+ * With spp > 1 every sample is its own job; the library keeps 28 bytes per
+ * pixel of scratch per in-flight launch (grown on demand, kept for reuse) for
+ * exact fixed-point colour sums and per-pixel sample counters, so results do
+ * not depend on the order in which samples finish.
+ * PR_ERR_OUT_OF_MEMORY if that scratch cannot be allocated. */
 pr_status pr_render(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
                     uint32_t width, uint32_t height,
                     float* out_rgb, float* out_t, int32_t* out_inst, void* hip_stream);
@@ -238,7 +243,8 @@ typedef struct {
 } pr_server_stats;
 
 /* Continuous-batching server: a scheduler thread admits queued requests
- * FIFO while their output footprint fits the budget, launches the admitted
+ * FIFO while their footprint (outputs, plus the per-sample scratch of
+ * requests with spp > 1) fits the budget, launches the admitted
  * ones together on a free stream while earlier launches are still running,
  * and records completion times.  Scenes stay resident on the device. */
 pr_status pr_server_create(const pr_server_opts* opts, pr_server** out);

@@ -28,6 +28,11 @@ struct LaunchCtx {
   hipEvent_t done = nullptr;
   bool in_use = false;
   int device = -1;
+  // per-pixel colour accumulators (3 x u64) and sample counters for
+  // multi-sample requests, grown on demand; sample_px_cap pixels
+  unsigned long long* sample_acc = nullptr;
+  uint32_t* sample_cnt = nullptr;
+  size_t sample_px_cap = 0;
   // graph cache for this context
   hipGraphExec_t graph = nullptr;
   size_t graph_bytes = 0;

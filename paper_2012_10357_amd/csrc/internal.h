@@ -67,7 +67,8 @@ struct alignas(16) SceneConstsDev {
 };
 static_assert(sizeof(SceneConstsDev) == 48, "scene constants");
 
-// One render request as seen by the kernel.  176 bytes.
+// One render request as seen by the kernel.  192 bytes.  A job is one
+// (pixel, sample); jobs of a tile are ordered sample-major: tile, sample, lane.
 struct alignas(16) ReqDev {
   float eye[3];
   float vfov_deg;
@@ -90,10 +91,12 @@ struct alignas(16) ReqDev {
   float* out_t;
   int32_t* out_inst;
   uint32_t* done_counter;  // optional: per-request finished-job counter (may be null)
+  unsigned long long* sample_acc;  // spp > 1: 32.32 fixed-point colour sums (W*H*3), zero between launches
+  uint32_t* sample_cnt;            // spp > 1: finished samples per pixel (W*H), zero between launches
 };
-static_assert(sizeof(ReqDev) == 176, "request record");
+static_assert(sizeof(ReqDev) == 192, "request record");
 
-// Work queue of one launch: a job is one pixel (all its samples).  When every
+// Work queue of one launch.  When every
 // request of the launch renders the same scene, that scene's top BVH nodes,
 // first instance records and constants are staged in LDS by every workgroup.
 struct alignas(16) QueueDev {

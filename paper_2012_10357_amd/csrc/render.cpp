@@ -216,7 +216,7 @@ void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_rende
   r.tiles_x = (w + tile_w - 1) / tile_w;
   const uint32_t tiles_y = (h + th - 1) / th;
   r.job_begin = job_begin;
-  r.job_end = job_begin + r.tiles_x * tiles_y * 64;
+  r.job_end = job_begin + r.tiles_x * tiles_y * 64 * o->spp;
   r.insts = s->d_insts;
   r.nodes = s->d_nodes;
   r.consts = s->d_consts;
@@ -257,6 +257,43 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
                           unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt) {
   LaunchCtx* c = acquire_ctx((uint32_t)reqs.size());
   if (!c) return set_error(PR_ERR_OUT_OF_MEMORY, "could not allocate a launch context");
+  // fixed-point colour accumulators and sample counters for requests with
+  // several samples per pixel (zero at allocation; each launch leaves them zero)
+  size_t need_px = 0;
+  for (const ReqDev& r : reqs)
+    if (r.spp > 1 && !r.sample_acc) need_px += (size_t)r.width * r.height;
+  if (need_px > c->sample_px_cap) {
+    // grow while the context is idle
+    if (c->sample_acc) hipFree(c->sample_acc);
+    if (c->sample_cnt) hipFree(c->sample_cnt);
+    c->sample_acc = nullptr;
+    c->sample_cnt = nullptr;
+    c->sample_px_cap = 0;
+    if (hipMalloc((void**)&c->sample_acc, need_px * 3 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&c->sample_cnt, need_px * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->sample_acc, 0, need_px * 3 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->sample_cnt, 0, need_px * sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (c->sample_acc) hipFree(c->sample_acc);
+      if (c->sample_cnt) hipFree(c->sample_cnt);
+      c->sample_acc = nullptr;
+      c->sample_cnt = nullptr;
+      release_ctx(c);
+      return set_error(PR_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of per-sample scratch", need_px * 28);
+    }
+    c->sample_px_cap = need_px;
+  }
+  std::vector<ReqDev> table(reqs);
+  {
+    size_t off = 0;
+    for (ReqDev& r : table) {
+      if (r.spp > 1 && !r.sample_acc) {
+        r.sample_acc = c->sample_acc + off * 3;
+        r.sample_cnt = c->sample_cnt + off;
+        off += (size_t)r.width * r.height;
+      }
+    }
+  }
   QueueDev q;
   std::memset(&q, 0, sizeof q);
   q.total_jobs = total_jobs;
@@ -273,7 +310,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     q.stage_consts = scenes[0]->d_consts;
   }
   std::memcpy(c->host, &q, sizeof q);
-  std::memcpy((char*)c->host + sizeof(QueueDev), reqs.data(), reqs.size() * sizeof(ReqDev));
+  std::memcpy((char*)c->host + sizeof(QueueDev), table.data(), table.size() * sizeof(ReqDev));
   const size_t bytes = sizeof(QueueDev) + reqs.size() * sizeof(ReqDev);
   LaunchCfg cfg{step_budget, grid_for(total_jobs)};
   hipError_t e;
@@ -354,9 +391,11 @@ pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes,
     if (inst && (st = check_device_ptr(inst, (size_t)w * h * 4, "out_inst", s->device)) != PR_OK) return st;
   }
   uint32_t tw = o->tile_w ? o->tile_w : (tile_w_override ? tile_w_override : tuned_for(s).tile_w);
+  const uint64_t tiles = (uint64_t)((w + tw - 1) / tw) * ((h + 64 / tw - 1) / (64 / tw));
+  if ((uint64_t)total_jobs + tiles * 64ull * o->spp > 0xF0000000ull)
+    return set_error(PR_ERR_INVALID_ARG, "too many pixel samples in one launch");
   ReqDev r;
   fill_req(r, s, cam, o, w, h, tw, rgb, t, inst, total_jobs);
-  if ((uint64_t)r.job_end > 0xF0000000ull) return set_error(PR_ERR_INVALID_ARG, "too many pixels in one launch");
   total_jobs = r.job_end;
   reqs.push_back(r);
   scenes.push_back(s);

@@ -100,6 +100,10 @@ struct Ticket {
   uint64_t id = 0;
   pr_request req{};
   uint64_t bytes = 0, off = 0;
+  // several samples per pixel: colour accumulators and sample counters,
+  // carved right after the outputs
+  unsigned long long* sample_acc = nullptr;
+  uint32_t* sample_cnt = nullptr;
   double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 admitted, 2 launched, 3 done
   pr_status status = PR_OK;
@@ -146,6 +150,15 @@ class HipExecutor : public Executor {
                                  t->req.height, t->req.out_rgb, t->req.out_t, t->req.out_inst, 0, total,
                                  false);
       if (st != PR_OK) return st;
+      if (t->sample_acc) {
+        // pool memory is reused: accumulators and counters must start at zero
+        const size_t bytes = (size_t)((char*)(t->sample_cnt + (size_t)t->req.width * t->req.height) -
+                                      (char*)t->sample_acc);
+        hipError_t e = hipMemsetAsync(t->sample_acc, 0, bytes, streams_[slot]);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(sample accumulators)");
+        reqs.back().sample_acc = t->sample_acc;
+        reqs.back().sample_cnt = t->sample_cnt;
+      }
     }
     int budget = budget_for(scenes[0], nullptr, 0);
     return launch_prepared(reqs, scenes, total, budget, graph_, nullptr, streams_[slot], events_[slot]);
@@ -214,7 +227,9 @@ struct pr_server {
   uint64_t footprint(const pr_request& r) const {
     uint64_t px = (uint64_t)r.width * r.height;
     auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
-    return up(px * 12) + up(px * 4) + up(px * 4);
+    uint64_t b = up(px * 12) + up(px * 4) + up(px * 4);
+    if (r.opts.spp > 1) b += up(px * 24) + up(px * 4);
+    return b;
   }
 
   void carve(Ticket* t) {
@@ -224,6 +239,11 @@ struct pr_server {
     t->req.out_rgb = reinterpret_cast<float*>(base);
     t->req.out_t = reinterpret_cast<float*>(base + up(px * 12));
     t->req.out_inst = reinterpret_cast<int32_t*>(base + up(px * 12) + up(px * 4));
+    if (t->req.opts.spp > 1) {
+      char* sb = base + up(px * 12) + up(px * 4) + up(px * 4);
+      t->sample_acc = reinterpret_cast<unsigned long long*>(sb);
+      t->sample_cnt = reinterpret_cast<uint32_t*>(sb + up(px * 24));
+    }
   }
 
   void loop() {

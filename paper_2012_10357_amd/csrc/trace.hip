@@ -133,7 +133,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   uint32_t req_i = 0;
   int px = 0, py = 0;
   uint32_t s = 0, spp = 1;
-  float acc_r = 0.f, acc_g = 0.f, acc_b = 0.f;
   float out_t = 0.f;
   int out_id = -1;
 
@@ -224,21 +223,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     begin_ray(r, K_PRIMARY, R->tmin, R->tmax);
   };
 
+  // A job is one sample.  With several samples per pixel the samples of a
+  // pixel run as separate jobs on any lanes of any workgroup.  Each adds its
+  // colour, in 32.32 fixed point, to the pixel's 64-bit accumulators with
+  // device-scope atomics (integer sums are exact, so the mean does not depend
+  // on the order the samples finish in), waits until those adds are
+  // performed, then bumps the pixel's sample counter.  The sample that
+  // completes the count takes the sums with atomic exchanges, which also
+  // clear the accumulators for the next launch, and writes the mean.
   auto finish_sample = [&](float cr, float cg, float cb) {
-    acc_r += cr; acc_g += cg; acc_b += cb;
-    ++s;
-    if (s < spp) {
-      primary_ray();
-      return;
-    }
-    const float inv = 1.0f / (float)spp;
     const size_t pix = (size_t)py * R->width + px;
+    if (s == 0) {
+      if (R->out_t) R->out_t[pix] = out_t;
+      if (R->out_inst) R->out_inst[pix] = out_id;
+    }
     float* o = R->out_rgb + pix * 3;
-    o[0] = acc_r * inv;
-    o[1] = acc_g * inv;
-    o[2] = acc_b * inv;
-    if (R->out_t) R->out_t[pix] = out_t;
-    if (R->out_inst) R->out_inst[pix] = out_id;
+    if (spp == 1) {
+      o[0] = cr;
+      o[1] = cg;
+      o[2] = cb;
+    } else {
+      // colours are >= 0 and far below 2^31, so 64-bit sums never overflow
+      constexpr float kFix = 4294967296.0f;  // 2^32
+      unsigned long long* acc = R->sample_acc + pix * 3;
+      atomicAdd(acc + 0, (unsigned long long)__float2ull_rn(cr * kFix));
+      atomicAdd(acc + 1, (unsigned long long)__float2ull_rn(cg * kFix));
+      atomicAdd(acc + 2, (unsigned long long)__float2ull_rn(cb * kFix));
+      // vmcnt also counts stores and atomics without return: wait until the
+      // three adds are acknowledged before the counter can reach its total
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      const uint32_t before = atomicAdd(&R->sample_cnt[pix], 1u);
+      if (before == spp - 1) {
+        const double scale = 1.0 / (4294967296.0 * (double)spp);
+        o[0] = (float)((double)atomicExch(acc + 0, 0ull) * scale);
+        o[1] = (float)((double)atomicExch(acc + 1, 0ull) * scale);
+        o[2] = (float)((double)atomicExch(acc + 2, 0ull) * scale);
+        atomicExch(&R->sample_cnt[pix], 0u);
+      }
+    }
     if (R->done_counter) atomicAdd(R->done_counter, 1u);
     has_job = false;
     mode = M_IDLE;
@@ -268,7 +290,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     eps = R->eps;
     spp = R->spp;
     uint32_t local = j - R->job_begin;
-    uint32_t tile = local >> 6, li = local & 63u;
+    const uint32_t per_tile = 64u * spp;
+    uint32_t tile = local / per_tile, rem = local - tile * per_tile;
+    uint32_t li = rem & 63u;
     uint32_t tw = R->tile_w, th = 64u / tw;
     uint32_t tx = tile % R->tiles_x, ty = tile / R->tiles_x;
     px = (int)(tx * tw + li % tw);
@@ -282,8 +306,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     has_job = true;
     job_evals = 0;
-    s = 0;
-    acc_r = acc_g = acc_b = 0.f;
+    s = rem >> 6;
     out_t = __builtin_inff();
     out_id = -1;
     primary_ray();

@@ -30,10 +30,15 @@ def _opts(side, spp=1):
     return W.RenderOpts(side, side, spp=spp, jitter=1 if spp > 1 else 0, max_steps=256)
 
 
-def _fp(side):
+def _fp(side, spp=1):
+    """Pool bytes of one request: colour, depth and instance outputs, plus
+    three 64-bit colour sums and a counter per pixel when spp > 1."""
     up = lambda b: (b + 255) // 256 * 256
     px = side * side
-    return up(px * 12) + 2 * up(px * 4)
+    b = up(px * 12) + 2 * up(px * 4)
+    if spp > 1:
+        b += up(px * 24) + up(px * 4)
+    return b
 
 
 def test_oversize_rejected_and_unregistered_scene(P, scene):
@@ -46,6 +51,24 @@ def test_oversize_rejected_and_unregistered_scene(P, scene):
     with pytest.raises(P.ProcrayError, match="not registered"):
         srv.submit(other, W.c2_camera(), _opts(64))
     assert srv.stats().rejected == 1
+    srv.close()
+
+
+def test_footprint_counts_per_sample_scratch(P, scene):
+    """A multi-sample request also reserves its per-sample colours and
+    counters: it fits a budget of exactly that size and not one byte less."""
+    need = _fp(256, spp=4)
+    srv = P.Server(need, max_inflight=1, simulated_us_per_mpix=100)
+    srv.add_scene(scene)
+    tk = srv.submit(scene, W.c2_camera(), _opts(256, spp=4))
+    srv.wait(tk, 10000)
+    assert srv.stats().pool_bytes_peak == need
+    srv.release(tk)
+    srv.close()
+    srv = P.Server(need - 1, max_inflight=1, simulated_us_per_mpix=100)
+    srv.add_scene(scene)
+    with pytest.raises(P.ProcrayError, match="OUT_OF_MEMORY"):
+        srv.submit(scene, W.c2_camera(), _opts(256, spp=4))
     srv.close()
 
 
@@ -100,7 +123,7 @@ def test_large_request_not_starved(P, scene):
 
 
 def test_wait_timeout_and_release_busy(P, scene):
-    srv = P.Server(_fp(512) * 2, max_inflight=1, simulated_us_per_mpix=200000)
+    srv = P.Server(_fp(512, spp=4), max_inflight=1, simulated_us_per_mpix=200000)
     srv.add_scene(scene)
     tk = srv.submit(scene, W.c2_camera(), _opts(512, spp=4))   # ~0.2 s simulated
     with pytest.raises(P.ProcrayError, match="TIMEOUT"):
