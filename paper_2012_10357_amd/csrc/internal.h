@@ -114,7 +114,7 @@ struct alignas(16) QueueDev {
 static_assert(sizeof(QueueDev) == 64, "queue header");
 
 constexpr uint32_t kLdsNodes = 128;   // 8 KB: the top seven BVH levels (breadth-first layout)
-constexpr uint32_t kLdsInsts = 64;    // 8 KB of instance records
+constexpr uint32_t kLdsInsts = 32;    // 4 KB of instance records
 constexpr uint32_t kLdsReqs = 8;      // request records staged per workgroup
 
 // Per-launch counters of the instrumented kernel.

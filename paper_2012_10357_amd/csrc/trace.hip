@@ -35,11 +35,15 @@ namespace pr {
 namespace {
 
 constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_IDLE = 4,
-                   M_NORMAL_READY = 5;
+                   M_NORMAL_READY = 5, M_WAIT = 6;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kLongJob = 192;   // evaluations after which a pixel counts as long-running
 constexpr uint32_t kChunk = 64;      // jobs a wave reserves per queue atomic (>= the 64 lanes)
-constexpr uint32_t K_PRIMARY = 0, K_SHADOW = 1, K_BOUNCE = 2, K_BSHADOW = 3;
+// ray kinds; odd kinds are shadow rays (any hit ends them).  K_HSHADOW is the
+// shadow ray of a primary hit handed off to another lane of the wave.
+constexpr uint32_t K_PRIMARY = 0, K_SHADOW = 1, K_BOUNCE = 2, K_BSHADOW = 3, K_HSHADOW = 5;
+// hand-off slot states
+constexpr uint32_t T_NONE = 0, T_POSTED = 1, T_TAKEN = 2, T_DONE = 3;
 
 __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
   // Wellons' lowbias32 integer hash (public domain): xor-shift / multiply.
@@ -98,6 +102,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   __shared__ const InstDev* nrm_inst[kWavesPerBlock][kWave];
   __shared__ float nrm_res[kWavesPerBlock][6][kWave];
   __shared__ uint8_t nrm_owner[kWavesPerBlock][kWave];
+  // Shadow rays of primary hits that go on to a mirror bounce are handed to
+  // idle lanes of the same wave, so the shadow ray and the bounce chain run
+  // side by side.  Slot = owner lane: shadow-ray origin and Lambert factor,
+  // replaced by the shaded primary colour when done; request and instance.
+  __shared__ float tk_val[kWavesPerBlock][4][kWave];
+  __shared__ uint32_t tk_ref[kWavesPerBlock][kWave];
+  __shared__ uint32_t tk_state[kWavesPerBlock][kWave];
+  __shared__ uint8_t tk_list[kWavesPerBlock][kWave];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
@@ -153,6 +165,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   float t = 0.f, t1 = 0.f, sigma = 1.f;
   int steps = 0;
   uint32_t job_evals = 0;   // estimator evaluations of the current pixel job
+  int help_owner = -1;      // K_HSHADOW: lane whose primary hit this shadow ray serves
+  bool donated = false;     // this lane's primary shadow ray was handed off
   float gx = 0.f, gy = 0.f, gz = 0.f;
 
   // shading stash
@@ -193,7 +207,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     leaf_i = 0;
     stack_mem[sp++][tid] = 0;
     mode = M_TRAVERSE;
-    if (COUNT) atomicAdd(&cnt_lds[28 + k], 1ull);
+    if (COUNT) atomicAdd(&cnt_lds[28 + (k == K_HSHADOW ? K_SHADOW : k)], 1ull);
   };
 
   auto primary_ray = [&]() {
@@ -266,13 +280,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     mode = M_IDLE;
   };
 
-  auto start_job = [&](uint32_t j) {
-    // locate the request (few requests: linear; many: binary search)
-    uint32_t a = 0, b = n_req;
-    while (b - a > 1) {
-      uint32_t m = (a + b) >> 1;
-      if (reqs[m].job_begin <= j) a = m; else b = m;
-    }
+  auto bind_request = [&](uint32_t a) {
     req_i = a;
     R = a < kLdsReqs ? &lds_reqs[a] : reqs + a;
     insts = R->insts;
@@ -289,6 +297,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     max_steps = R->max_steps;
     eps = R->eps;
     spp = R->spp;
+  };
+
+  auto start_job = [&](uint32_t j) {
+    // locate the request (few requests: linear; many: binary search)
+    uint32_t a = 0, b = n_req;
+    while (b - a > 1) {
+      uint32_t m = (a + b) >> 1;
+      if (reqs[m].job_begin <= j) a = m; else b = m;
+    }
+    bind_request(a);
     uint32_t local = j - R->job_begin;
     const uint32_t per_tile = 64u * spp;
     uint32_t tile = local / per_tile, rem = local - tile * per_tile;
@@ -418,6 +436,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     mode = M_NORMAL;
   };
 
+  // mirror bounce from the primary hit: r = d - 2 (d.n) n, origin offset
+  // along the normal
+  auto start_bounce = [&]() {
+    float dn = bounce_ray.dx * hnx + bounce_ray.dy * hny + bounce_ray.dz * hnz;
+    float rx = bounce_ray.dx - 2.f * dn * hnx;
+    float ry = bounce_ray.dy - 2.f * dn * hny;
+    float rz = bounce_ray.dz - 2.f * dn * hnz;
+    const float off = R->shadow_offset;
+    Ray br{hpx + off * hnx, hpy + off * hny, hpz + off * hnz, rx, ry, rz};
+    begin_ray(br, K_BOUNCE, 0.0f, R->tmax);
+  };
+
+  // run the handed-off shadow ray of lane `owner` (another lane's, or this
+  // lane's own when nobody took it)
+  auto run_handoff = [&](int owner) {
+    help_owner = owner;
+    if (owner != lane) {
+      bind_request(tk_ref[wv][owner] >> 14);
+      has_job = true;
+      job_evals = 0;
+    }
+    const float sx = tk_val[wv][0][owner], sy = tk_val[wv][1][owner], sz = tk_val[wv][2][owner];
+    float vx = sc->light[0] - sx, vy = sc->light[1] - sy, vz = sc->light[2] - sz;
+    float dist = __builtin_sqrtf(vx * vx + vy * vy + vz * vz);
+    float idist = 1.0f / dist;
+    Ray srr{sx, sy, sz, vx * idist, vy * idist, vz * idist};
+    begin_ray(srr, K_HSHADOW, 0.0f, dist);
+  };
+
   // normal finished: shade prep, spawn the shadow ray (or skip it)
   auto after_normal = [&]() {
     const InstDev& I = *inst_ptr(cur_slot);
@@ -439,6 +486,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     hpx = hx; hpy = hy; hpz = hz; hnx = nx; hny = ny; hnz = nz;
     if (kind == K_PRIMARY) p_rho = I.refl;
     const float off = R->shadow_offset;
+    if (kind == K_PRIMARY && R->shadows && R->bounces >= 1 && I.refl > 0.f) {
+      // hand the shadow ray to an idle lane and start the mirror bounce now
+      tk_val[wv][0][lane] = hx + off * nx;
+      tk_val[wv][1][lane] = hy + off * ny;
+      tk_val[wv][2][lane] = hz + off * nz;
+      tk_val[wv][3][lane] = sh_lam;
+      tk_ref[wv][lane] = (req_i << 14) | (uint32_t)cur_slot;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      tk_state[wv][lane] = T_POSTED;
+      donated = true;
+      start_bounce();
+      return;
+    }
     if (R->shadows) {
       float sx = hx + off * nx, sy = hy + off * ny, sz = hz + off * nz;
       float vx = sc->light[0] - sx, vy = sc->light[1] - sy, vz = sc->light[2] - sz;
@@ -462,6 +522,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     cb = sh_ab * (amb + V * sh_lam * sc->light_rgb[2]);
   };
 
+  // The owner of a handed-off shadow ray, its bounce colour kept in p_c*:
+  // combine once the primary colour is published, run the shadow ray itself
+  // if no lane took it, or wait for the lane that did.
+  auto collect = [&]() {
+    const uint32_t st = tk_state[wv][lane];
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (st == T_DONE) {
+      const float rho = p_rho;
+      const float cr = tk_val[wv][0][lane], cg = tk_val[wv][1][lane], cb = tk_val[wv][2][lane];
+      tk_state[wv][lane] = T_NONE;
+      donated = false;
+      finish_sample((1.f - rho) * cr + rho * p_cr, (1.f - rho) * cg + rho * p_cg,
+                    (1.f - rho) * cb + rho * p_cb);
+    } else if (st == T_POSTED) {
+      tk_state[wv][lane] = T_TAKEN;
+      run_handoff(lane);
+    } else {
+      mode = M_WAIT;
+    }
+  };
+
+  // the mirror bounce's colour is known: blend with the primary colour
+  auto end_bounce = [&](float br, float bg, float bb) {
+    if (donated) {
+      p_cr = br;
+      p_cg = bg;
+      p_cb = bb;
+      collect();
+      return;
+    }
+    const float rho = p_rho;
+    finish_sample((1.f - rho) * p_cr + rho * br, (1.f - rho) * p_cg + rho * bg,
+                  (1.f - rho) * p_cb + rho * bb);
+  };
+
   // a ray has finished traversal: move the pixel's pipeline forward
   auto ray_done = [&]() {
     switch (kind) {
@@ -482,14 +577,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         lambert(occluded ? 0.f : 1.f, cr, cg, cb);
         if (R->bounces >= 1 && p_rho > 0.f) {
           p_cr = cr; p_cg = cg; p_cb = cb;
-          // mirror direction r = d - 2 (d.n) n from the primary hit
-          float dn = bounce_ray.dx * hnx + bounce_ray.dy * hny + bounce_ray.dz * hnz;
-          float rx = bounce_ray.dx - 2.f * dn * hnx;
-          float ry = bounce_ray.dy - 2.f * dn * hny;
-          float rz = bounce_ray.dz - 2.f * dn * hnz;
-          const float off = R->shadow_offset;
-          Ray br{hpx + off * hnx, hpy + off * hny, hpz + off * hnz, rx, ry, rz};
-          begin_ray(br, K_BOUNCE, 0.0f, R->tmax);
+          start_bounce();
         } else {
           finish_sample(cr, cg, cb);
         }
@@ -497,28 +585,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       }
       case K_BOUNCE: {
         if (best_slot < 0) {
-          const float rho = p_rho;
-          finish_sample((1.f - rho) * p_cr + rho * sc->background[0],
-                        (1.f - rho) * p_cg + rho * sc->background[1],
-                        (1.f - rho) * p_cb + rho * sc->background[2]);
+          end_bounce(sc->background[0], sc->background[1], sc->background[2]);
         } else {
           start_normal(best_slot, limit);
         }
         break;
       }
-      default: {  // K_BSHADOW
+      case K_BSHADOW: {
         float cr, cg, cb;
         lambert(occluded ? 0.f : 1.f, cr, cg, cb);
-        const float rho = p_rho;
-        finish_sample((1.f - rho) * p_cr + rho * cr, (1.f - rho) * p_cg + rho * cg,
-                      (1.f - rho) * p_cb + rho * cb);
+        end_bounce(cr, cg, cb);
+        break;
+      }
+      default: {  // K_HSHADOW: shade the owner's primary hit, publish it
+        const int ow = help_owner;
+        const InstDev& I = *inst_ptr((int)(tk_ref[wv][ow] & 0x3fffu));
+        const float lam = tk_val[wv][3][ow];
+        const float V = occluded ? 0.f : 1.f;
+        const float amb = sc->ambient;
+        tk_val[wv][0][ow] = I.albedo[0] * (amb + V * lam * sc->light_rgb[0]);
+        tk_val[wv][1][ow] = I.albedo[1] * (amb + V * lam * sc->light_rgb[1]);
+        tk_val[wv][2][ow] = I.albedo[2] * (amb + V * lam * sc->light_rgb[2]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        tk_state[wv][ow] = T_DONE;
+        help_owner = -1;
+        if (ow == lane) {
+          collect();
+        } else {
+          has_job = false;
+          mode = M_IDLE;
+        }
         break;
       }
     }
   };
 
   // ---------------- main loop
+  tk_state[wv][lane] = T_NONE;
   for (;;) {
+    // owners waiting for a handed-off shadow ray; then idle lanes take the
+    // posted ones (in lane order) before new jobs
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (has_job && mode == M_WAIT) collect();
+    const unsigned long long posted = __ballot(tk_state[wv][lane] == T_POSTED);
+    if (posted) {
+      const unsigned long long idle = __ballot(!has_job);
+      if (idle) {
+        const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (tk_state[wv][lane] == T_POSTED) tk_list[wv][__popcll(posted & lt)] = (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (!has_job) {
+          const uint32_t r = (uint32_t)__popcll(idle & lt);
+          if (r < (uint32_t)__popcll(posted)) {
+            const int owner = tk_list[wv][r];
+            tk_state[wv][owner] = T_TAKEN;
+            run_handoff(owner);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
     // Refill idle lanes.  Each wave holds a reservation of consecutive job
     // indices [res_cur, res_end) and takes a fresh chunk of kChunk jobs with
     // one atomic only when the reservation cannot serve all idle lanes; jobs
@@ -554,7 +686,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
     // control: advance every lane to its next estimator evaluation
     auto control = [&]() {
-      while (has_job && mode != M_MARCH && mode != M_NORMAL) {
+      while (has_job && mode != M_MARCH && mode != M_NORMAL && mode != M_WAIT) {
         if (mode == M_TRAVERSE) {
           traverse();
         } else if (mode == M_NORMAL_READY) {
@@ -647,7 +779,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float v = sigma * de;
         if (v < eps) {
           // hit at t
-          if (kind == K_SHADOW || kind == K_BSHADOW) {
+          if (kind & 1u) {
             occluded = true;
             mode = M_RAYDONE;
           } else {
