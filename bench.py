@@ -331,8 +331,11 @@ def main():
                      "traffic": None, "kernel": "trace_kernel", "kernel_ms": round(kern_ms, 4),
                      "flops_per_launch": flops_per_frame},
     }
+    cus, wg_per_cu = P.launch_shape()
+    out["roofline"]["grid"] = {"compute_units": cus, "workgroups_per_cu": wg_per_cu}
     print(f"# frame: {rays_per_frame} rays, {flops_per_frame / 1e9:.2f} GFLOP, "
-          f"kernel {kern_ms:.3f} ms (min {per_launch_ms.min():.3f})", file=sys.stderr, flush=True)
+          f"kernel {kern_ms:.3f} ms (min {per_launch_ms.min():.3f}), "
+          f"{cus} CUs x {wg_per_cu} workgroups", file=sys.stderr, flush=True)
     traffic = committed_traffic()
     out["roofline"]["traffic"] = traffic
     sc.close()

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 1
+#define PR_ABI_VERSION 2
 
 typedef enum {
   PR_OK = 0,
@@ -68,8 +68,14 @@ typedef enum {
 typedef struct { float lo[3], hi[3]; } pr_aabb;                          /* local space */
 
 /* One procedural geometry: its type, local AABB and parameters (Sec. 4.1,
- * listing "Procedural geometry creation": a geometry is an AABB). 60 bytes. */
-typedef struct { uint32_t type; pr_aabb aabb; float params[8]; } pr_geometry;
+ * listing "Procedural geometry creation": a geometry is an AABB), and an
+ * optional cutting plane (Fig. 5 shows the Julia set cut by planes).
+ *   cut = {nx, ny, nz, d}: only the local half-space n.p <= d is kept, i.e.
+ *   the estimator becomes max(DE(p), n.p - d), the CSG intersection of the
+ *   primitive with the half-space.  n = (0, 0, 0) means no cut.  A non-zero
+ *   n is normalised by pr_scene_create (d is divided by the same |n|).
+ * 76 bytes. */
+typedef struct { uint32_t type; pr_aabb aabb; float params[8]; float cut[4]; } pr_geometry;
 
 /* One instance: geometry and material indices plus a row-major 3x4
  * local-to-world affine [A | b] (column vectors: world = A local + b).
@@ -278,6 +284,11 @@ const char* pr_last_error(void);
 uint32_t pr_abi_version(void);
 /* Number of HIP devices visible (0 when none); never fails. */
 uint32_t pr_device_count(void);
+/* Launch shape of the persistent kernel on the current device: compute units
+ * and resident workgroups (256 threads each) per compute unit, as used to
+ * size every launch's grid.  Both host, non-NULL.  PR_ERR_DEVICE without a
+ * GPU. */
+pr_status pr_launch_shape(uint32_t* compute_units, uint32_t* workgroups_per_cu);
 
 #ifdef __cplusplus
 }

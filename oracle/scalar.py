@@ -135,7 +135,11 @@ class ScalarScene:
             g = int(scene.inst_geom[k])
             m = int(scene.inst_mat[k])
             aabb = [float(v) for v in scene.geom_aabb[g]]
-            self.inst.append(dict(
+            raw = getattr(scene, "geom_cut", None)
+            cut = [0.0, 0.0, 0.0, 0.0] if raw is None else [float(v) for v in raw[g]]
+            nn = math.sqrt(cut[0] * cut[0] + cut[1] * cut[1] + cut[2] * cut[2])
+            cut = [v / nn for v in cut] if nn > 0 else None
+            self.inst.append(dict(cut=cut,
                 Ainv=Ainv, b=b, sigma=sigma, lo=aabb[0:3], hi=aabb[3:6],
                 gt=int(scene.geom_type[g]), prm=[float(v) for v in scene.geom_params[g]],
                 albedo=[float(v) for v in scene.mat_albedo[m]], refl=float(scene.mat_refl[m])))
@@ -167,10 +171,22 @@ def _clip(ol, dl, lo, hi, tmin, tmax):
     return (t0, t1) if t0 <= t1 else None
 
 
+def _cut_de(ins, p):
+    """Estimator of the instance, intersected with its kept half-space
+    n.p <= d when it has a cutting plane (Fig. 5)."""
+    v, _ = _de(ins["gt"], p, ins["prm"])
+    c = ins["cut"]
+    if c is not None and v == v:
+        g = c[0] * p[0] + c[1] * p[1] + c[2] * p[2] - c[3]
+        if g > v:
+            v = g
+    return v
+
+
 def _march(ins, ol, dl, t0, t1, n_max, eps):
     t = t0
     for _ in range(n_max):
-        v, _ = _de(ins["gt"], _add(ol, _mul(dl, t)), ins["prm"])
+        v = _cut_de(ins, _add(ol, _mul(dl, t)))
         v *= ins["sigma"]
         if v != v:
             return None
@@ -217,7 +233,7 @@ def _normal(ins, o, d, t, h_fd):
     g = []
     for ax in range(3):
         e = [0.0, 0.0, 0.0]; e[ax] = h
-        g.append(_de(ins["gt"], _add(p, e), ins["prm"])[0] - _de(ins["gt"], _sub(p, e), ins["prm"])[0])
+        g.append(_cut_de(ins, _add(p, e)) - _cut_de(ins, _sub(p, e)))
     nw = _mtv(ins["Ainv"], g)
     ln = _len(nw)
     return _mul(d, -1.0) if not ln > 0 else _mul(nw, 1.0 / ln)

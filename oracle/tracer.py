@@ -89,12 +89,38 @@ class Prepared:
     hi: np.ndarray       # (N, 3)
     gtype: np.ndarray    # (N,)
     prm: np.ndarray      # (N, 8)
+    cut: np.ndarray      # (N, 4): unit normal n and offset d of the kept half-space n.p <= d; zeros = none
     albedo: np.ndarray   # (N, 3)
     refl: np.ndarray     # (N,)
     light: np.ndarray
     light_rgb: np.ndarray
     ambient: float
     background: np.ndarray
+
+
+def unit_cuts(scene) -> np.ndarray:
+    """Cutting planes per geometry (Fig. 5: the Julia set cut by planes) as
+    (n / |n|, d / |n|), so that n.p - d is the signed distance to the plane;
+    a zero normal (or no ``geom_cut`` at all) means no cut."""
+    G = len(scene.geom_type)
+    raw = getattr(scene, "geom_cut", None)
+    c = np.zeros((G, 4)) if raw is None else np.asarray(raw, np.float64).reshape(G, 4).copy()
+    nn = np.linalg.norm(c[:, :3], axis=1)
+    on = nn > 0
+    c[on] /= nn[on, None]
+    return c
+
+
+def apply_cut(v, pts, cut):
+    """CSG intersection of a primitive with its kept half-space: the
+    estimator becomes max(DE, n.p - d) where a cut is set (a NaN estimate
+    stays NaN).  ``cut`` is (m, 4) or (4,) per point."""
+    cut = np.broadcast_to(np.asarray(cut, np.float64), (pts.shape[0], 4))
+    on = np.any(cut[:, :3] != 0.0, axis=1)
+    if not on.any():
+        return v
+    g = np.einsum("mi,mi->m", pts, cut[:, :3]) - cut[:, 3]
+    return np.where(on, np.maximum(v, g), v)
 
 
 def prepare(scene) -> Prepared:
@@ -117,6 +143,7 @@ def prepare(scene) -> Prepared:
         A=A, b=b, Ainv=Ainv, sigma=sigma, lo=aabb[:, 0:3], hi=aabb[:, 3:6],
         gtype=np.asarray(scene.geom_type, np.int64)[g],
         prm=np.asarray(scene.geom_params, np.float64)[g],
+        cut=unit_cuts(scene)[g],
         albedo=np.asarray(scene.mat_albedo, np.float64)[mat],
         refl=np.asarray(scene.mat_refl, np.float64)[mat],
         light=np.asarray(scene.light_pos, np.float64),
@@ -200,10 +227,11 @@ def slab(o_l, d_l, lo, hi, tmin, tmax):
     return t0, t1, (t0 <= t1) & ~empty
 
 
-def march(gtype, o_l, d_l, t0, t1, prm, sigma, n_max, eps):
+def march(gtype, o_l, d_l, t0, t1, prm, sigma, n_max, eps, cut=None):
     """Sphere tracing of one primitive type over many (ray, instance) pairs.
 
-    For each pair: t = t0; repeat at most n_max times: v = sigma DE(o' + t d');
+    For each pair: t = t0; repeat at most n_max times: v = sigma DE(o' + t d')
+    (DE cut by the pair's plane when ``cut`` is given, see apply_cut);
     if v < eps: hit at t; t += v; if t > t1: miss.  Running out of steps is a
     miss; a NaN value ends the march as a miss.  Returns the full histories
     (t_i, v_i, iterations_i) for the diagnostics and the work count.
@@ -222,6 +250,8 @@ def march(gtype, o_l, d_l, t0, t1, prm, sigma, n_max, eps):
             break
         pts = o_l[idx] + t[idx, None] * d_l[idx]
         v, it = de_eval(gtype, pts, prm[idx])
+        if cut is not None:
+            v = apply_cut(v, pts, cut[idx])
         v = sigma[idx] * v
         T[idx, i] = t[idx]
         V[idx, i] = v
@@ -330,7 +360,7 @@ def trace(prep, o, d, tmin, tmax, opts, mode, source=None, counts=None):
     for gt in np.unique(prep.gtype[K]) if P else []:
         sel = np.nonzero(prep.gtype[K] == gt)[0]
         h = march(int(gt), OL[sel], DL[sel], T0[sel], T1[sel], prep.prm[K[sel]],
-                  prep.sigma[K[sel]], n_max, eps)
+                  prep.sigma[K[sel]], n_max, eps, cut=prep.cut[K[sel]])
         res["out"][sel] = h["out"]; res["thit"][sel] = h["thit"]; res["n"][sel] = h["n"]
         hist[int(gt)] = (sel, h)
 
@@ -446,6 +476,8 @@ def normals(prep, inst, ol, dl, t, d_world, h_fd, counts=None):
             dp = h_l[sel, None] * e[None, :]
             vp, itp = de_eval(int(gt), p_l[sel] + dp, prm)
             vm, itm = de_eval(int(gt), p_l[sel] - dp, prm)
+            vp = apply_cut(vp, p_l[sel] + dp, prep.cut[inst[sel]])
+            vm = apply_cut(vm, p_l[sel] - dp, prep.cut[inst[sel]])
             g[sel, ax] = vp - vm
             if counts is not None:
                 counts.normal_evals[gt] += 2 * sel.size

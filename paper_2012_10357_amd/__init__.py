@@ -31,7 +31,7 @@ EXPORTS = [
     "pr_scene_destroy", "pr_render", "pr_render_counts", "pr_render_batch", "pr_autotune",
     "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
-    "pr_abi_version", "pr_device_count",
+    "pr_abi_version", "pr_device_count", "pr_launch_shape",
 ]
 
 
@@ -48,7 +48,7 @@ class Aabb(C.Structure):
 
 
 class Geometry(C.Structure):
-    _fields_ = [("type", C.c_uint32), ("aabb", Aabb), ("params", C.c_float * 8)]
+    _fields_ = [("type", C.c_uint32), ("aabb", Aabb), ("params", C.c_float * 8), ("cut", C.c_float * 4)]
 
 
 class Instance(C.Structure):
@@ -116,7 +116,7 @@ class ServerStats(C.Structure):
                 ("pool_bytes_in_use", C.c_uint64), ("pool_bytes_peak", C.c_uint64)]
 
 
-assert C.sizeof(Geometry) == 60 and C.sizeof(Instance) == 56 and C.sizeof(Material) == 16
+assert C.sizeof(Geometry) == 76 and C.sizeof(Instance) == 56 and C.sizeof(Material) == 16
 assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(RenderOptsC) == 64
 assert C.sizeof(BvhNode) == 32
 
@@ -152,6 +152,7 @@ def lib():
         "pr_server_release": [P, U64],
         "pr_server_stats_get": [P, P],
         "pr_server_destroy": [P],
+        "pr_launch_shape": [C.POINTER(U32), C.POINTER(U32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -200,6 +201,9 @@ class Scene:
             geoms[g].aabb.lo = _arr(C.c_float * 3, desc.geom_aabb[g, :3])
             geoms[g].aabb.hi = _arr(C.c_float * 3, desc.geom_aabb[g, 3:])
             geoms[g].params = _arr(C.c_float * 8, desc.geom_params[g])
+            cut = getattr(desc, "geom_cut", None)
+            if cut is not None:
+                geoms[g].cut = _arr(C.c_float * 4, cut[g])
         N = len(desc.inst_geom)
         insts = (Instance * N)()
         for i in range(N):
@@ -354,6 +358,14 @@ class Server:
 
 def device_count() -> int:
     return int(lib().pr_device_count())
+
+
+def launch_shape():
+    """(compute units, resident 256-thread workgroups per compute unit) of the
+    persistent kernel on the current device."""
+    cu, wg = C.c_uint32(0), C.c_uint32(0)
+    _check(lib().pr_launch_shape(C.byref(cu), C.byref(wg)))
+    return int(cu.value), int(wg.value)
 
 
 def abi_version() -> int:

@@ -48,6 +48,7 @@ void release_ctx(LaunchCtx* c);
 // The scene object behind the opaque handle.
 struct pr_scene {
   std::vector<pr::InstDev> host_insts;   // user order
+  std::vector<float> host_shade;         // user order: albedo rgb, reflectivity
   std::vector<float> world_aabb;         // 6 per instance
   std::vector<pr::HostNode> nodes;       // BVH, children adjacent, breadth-first
   std::vector<pr::NodeDev> dnodes;       // device layout: child boxes in the parent
@@ -59,6 +60,7 @@ struct pr_scene {
   pr::InstDev* d_insts = nullptr;        // leaf order
   pr::NodeDev* d_nodes = nullptr;
   pr::SceneConstsDev* d_consts = nullptr;
+  float* d_shade = nullptr;              // leaf order
   uint64_t device_bytes = 0;
   hipEvent_t last_use = nullptr;         // last launch reading this scene
   std::mutex mu;

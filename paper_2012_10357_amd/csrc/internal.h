@@ -3,8 +3,8 @@
 // The paper keeps per-instance data minimal so that traversal needs few
 // resources (Sec. 4.1.1: the local root signature only indexes an instance
 // buffer held globally).  Here each instance is one 128-byte record holding
-// everything its intersection and shading need, so a lane loads it once per
-// candidate; BVH nodes are 32 bytes.
+// everything its intersection needs, so a lane loads it once per candidate;
+// the material, needed only when a hit is shaded, sits in a separate array.
 #pragma once
 #include <stdint.h>
 
@@ -24,9 +24,8 @@ struct alignas(16) InstDev {
   float hi[3];
   float sigma;       // smallest singular value of A: local distance -> world lower bound
   uint32_t type;
-  float prm[8];      // kernel-ready parameters, see pack_params()
-  float albedo[3];
-  float refl;
+  float prm[8];      // kernel-ready parameters, see pack_params(); prm[7] = instance index bits
+  float cut[4];      // cutting plane n.p <= d (unit n); n = 0: none
 };
 static_assert(sizeof(InstDev) == 128, "instance record must stay 128 bytes");
 
@@ -64,8 +63,10 @@ struct alignas(16) SceneConstsDev {
   uint32_t n_inst;
   float background[3];
   uint32_t n_nodes;
+  const float* shade;  // per instance slot (BVH leaf order): albedo rgb, reflectivity
+  const void* pad;
 };
-static_assert(sizeof(SceneConstsDev) == 48, "scene constants");
+static_assert(sizeof(SceneConstsDev) == 64, "scene constants");
 
 // One render request as seen by the kernel.  192 bytes.  A job is one
 // (pixel, sample); jobs of a tile are ordered sample-major: tile, sample, lane.
@@ -115,7 +116,7 @@ static_assert(sizeof(QueueDev) == 64, "queue header");
 
 constexpr uint32_t kLdsNodes = 128;   // 8 KB: the top seven BVH levels (breadth-first layout)
 constexpr uint32_t kLdsInsts = 32;    // 4 KB of instance records
-constexpr uint32_t kLdsReqs = 8;      // request records staged per workgroup
+constexpr uint32_t kLdsReqs = 4;      // request records staged per workgroup
 
 // Per-launch counters of the instrumented kernel.
 constexpr int kNumCounts = PR_NUM_COUNTS;

@@ -429,6 +429,21 @@ pr_status pr_render(pr_scene* s, const pr_camera* cam, const pr_render_opts* opt
   }
 }
 
+pr_status pr_launch_shape(uint32_t* compute_units, uint32_t* workgroups_per_cu) {
+  if (!compute_units || !workgroups_per_cu) return set_error(PR_ERR_INVALID_ARG, "NULL argument");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(PR_ERR_DEVICE, "no HIP device");
+  }
+  const int cus = device_cu_count();
+  if (cus <= 0) return set_error(PR_ERR_DEVICE, "could not query the compute units");
+  if (g_blocks_per_cu == 0) g_blocks_per_cu = occupancy_blocks_per_cu();
+  *compute_units = (uint32_t)cus;
+  *workgroups_per_cu = (uint32_t)g_blocks_per_cu;
+  return ok();
+}
+
 pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_opts* opts, uint32_t w,
                            uint32_t h, float* out_rgb, uint64_t* counts) {
   try {

@@ -381,6 +381,14 @@ int bvh_depth(const std::vector<HostNode>& nodes, uint32_t ni) {
 
 }  // namespace
 
+// C ABI struct layouts (the Python binding asserts the same sizes)
+static_assert(sizeof(pr_geometry) == 76, "pr_geometry layout");
+static_assert(sizeof(pr_instance) == 56, "pr_instance layout");
+static_assert(sizeof(pr_material) == 16, "pr_material layout");
+static_assert(sizeof(pr_scene_consts) == 40, "pr_scene_consts layout");
+static_assert(sizeof(pr_camera) == 40, "pr_camera layout");
+static_assert(sizeof(pr_render_opts) == 64, "pr_render_opts layout");
+
 extern "C" {
 
 uint32_t pr_abi_version(void) { return PR_ABI_VERSION; }
@@ -406,7 +414,7 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
     if (!finite3(consts->light_pos, 3) || !finite3(consts->light_rgb, 3) ||
         !std::isfinite(consts->ambient) || !finite3(consts->background, 3))
       return set_error(PR_ERR_INVALID_ARG, "non-finite scene constants");
-    std::vector<float> packed(8 * (size_t)n_geom);
+    std::vector<float> packed(8 * (size_t)n_geom), cuts(4 * (size_t)n_geom);
     for (uint32_t g = 0; g < n_geom; ++g) {
       const pr_aabb& b = geoms[g].aabb;
       if (!finite3(b.lo, 3) || !finite3(b.hi, 3))
@@ -418,6 +426,17 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
         std::string m = "geometry " + std::to_string(g) + ": " + pr_last_error();
         return set_error(st, "%s", m.c_str());
       }
+      // cutting plane (Fig. 5): keep n.p <= d, n normalised here
+      const float* c = geoms[g].cut;
+      if (!finite3(c, 4)) return set_error(PR_ERR_INVALID_ARG, "geometry %u: non-finite cutting plane", g);
+      const double nn = std::sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]);
+      if (nn == 0.0) {
+        for (int k = 0; k < 4; ++k) cuts[4 * g + k] = 0.f;
+      } else if (!(nn > 1e-12)) {
+        return set_error(PR_ERR_INVALID_ARG, "geometry %u: cutting-plane normal too small", g);
+      } else {
+        for (int k = 0; k < 4; ++k) cuts[4 * g + k] = (float)((double)c[k] / nn);
+      }
     }
     for (uint32_t m = 0; m < n_mat; ++m) {
       if (!finite3(mats[m].albedo, 3) || !std::isfinite(mats[m].reflectivity) ||
@@ -426,6 +445,7 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
     }
     auto* s = new pr_scene();
     s->host_insts.resize(n_inst);
+    s->host_shade.resize(4 * (size_t)n_inst);
     s->world_aabb.resize(6 * (size_t)n_inst);
     for (uint32_t i = 0; i < n_inst; ++i) {
       const pr_instance& in = insts[i];
@@ -458,8 +478,9 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
       for (int k = 0; k < 8; ++k) d.prm[k] = packed[8 * in.geometry + k];
       uint32_t uid = i;
       std::memcpy(&d.prm[7], &uid, 4);
-      for (int k = 0; k < 3; ++k) d.albedo[k] = mats[in.material].albedo[k];
-      d.refl = mats[in.material].reflectivity;
+      for (int k = 0; k < 4; ++k) d.cut[k] = cuts[4 * in.geometry + k];
+      for (int k = 0; k < 3; ++k) s->host_shade[4 * (size_t)i + k] = mats[in.material].albedo[k];
+      s->host_shade[4 * (size_t)i + 3] = mats[in.material].reflectivity;
       s->n_types_present |= 1u << g.type;
       // world AABB: bounds of the 8 transformed corners (double)
       double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -502,9 +523,12 @@ static void free_device(pr_scene* s) {
   if (s->d_insts) hipFree(s->d_insts);
   if (s->d_nodes) hipFree(s->d_nodes);
   if (s->d_consts) hipFree(s->d_consts);
+  if (s->d_shade) hipFree(s->d_shade);
   s->d_insts = nullptr;
   s->d_nodes = nullptr;
   s->d_consts = nullptr;
+  s->d_shade = nullptr;
+  s->consts.shade = nullptr;
   s->uploaded = false;
   s->device_bytes = 0;
 }
@@ -530,9 +554,19 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::vector<InstDev> leaf(s->order.size());
-    for (size_t k = 0; k < s->order.size(); ++k) leaf[k] = s->host_insts[s->order[k]];
+    std::vector<float> leaf_shade(4 * s->order.size());
+    for (size_t k = 0; k < s->order.size(); ++k) {
+      leaf[k] = s->host_insts[s->order[k]];
+      for (int c = 0; c < 4; ++c) leaf_shade[4 * k + c] = s->host_shade[4 * (size_t)s->order[k] + c];
+    }
     const size_t bi = leaf.size() * sizeof(InstDev), bn = s->dnodes.size() * sizeof(NodeDev);
+    const size_t bs = leaf_shade.size() * sizeof(float);
     if ((e = hipMalloc((void**)&s->d_insts, bi)) != hipSuccess) return hip_fail(e, "hipMalloc(instances)");
+    if ((e = hipMalloc((void**)&s->d_shade, bs)) != hipSuccess) {
+      free_device(s);
+      return hip_fail(e, "hipMalloc(materials)");
+    }
+    s->consts.shade = s->d_shade;
     if ((e = hipMalloc((void**)&s->d_nodes, bn)) != hipSuccess) {
       free_device(s);
       return hip_fail(e, "hipMalloc(nodes)");
@@ -543,6 +577,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
     }
     if ((e = hipMemcpy(s->d_insts, leaf.data(), bi, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(s->d_nodes, s->dnodes.data(), bn, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->d_shade, leaf_shade.data(), bs, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(s->d_consts, &s->consts, sizeof(SceneConstsDev), hipMemcpyHostToDevice)) !=
             hipSuccess) {
       free_device(s);
@@ -553,7 +588,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
         return hip_fail(e, "hipEventCreate");
     }
     s->device = dev;
-    s->device_bytes = bi + bn + sizeof(SceneConstsDev);
+    s->device_bytes = bi + bn + bs + sizeof(SceneConstsDev);
     s->uploaded = true;
     return ok();
   } catch (const std::bad_alloc&) {

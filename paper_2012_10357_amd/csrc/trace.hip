@@ -37,7 +37,7 @@ namespace {
 constexpr uint32_t M_TRAVERSE = 0, M_MARCH = 1, M_NORMAL = 2, M_RAYDONE = 3, M_IDLE = 4,
                    M_NORMAL_READY = 5, M_WAIT = 6;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr uint32_t kLongJob = 192;   // evaluations after which a pixel counts as long-running
+constexpr uint32_t kLongJob = 48;    // evaluations after which a pixel counts as long-running
 constexpr uint32_t kChunk = 64;      // jobs a wave reserves per queue atomic (>= the 64 lanes)
 // ray kinds; odd kinds are shadow rays (any hit ends them).  K_HSHADOW is the
 // shadow ray of a primary hit handed off to another lane of the wave.
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                                                        int step_budget,
                                                        unsigned long long* __restrict__ counts) {
   __shared__ uint16_t stack_mem[kStackDepth][kBlock];
-  __shared__ unsigned long long cnt_lds[kNumCounts];
+  __shared__ unsigned long long cnt_lds[COUNT ? kNumCounts : 1];
   __shared__ NodeDev lds_nodes[kLdsNodes];
   __shared__ InstDev lds_insts[kLdsInsts];
   __shared__ ReqDev lds_reqs[kLdsReqs];
@@ -110,6 +110,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   __shared__ uint32_t tk_ref[kWavesPerBlock][kWave];
   __shared__ uint32_t tk_state[kWavesPerBlock][kWave];
   __shared__ uint8_t tk_list[kWavesPerBlock][kWave];
+  // cutting plane of the candidate being marched, along its local ray:
+  // n.(o' + t d') - d = x + t y; x = -inf when the instance has no cut
+  __shared__ float2 cut_line[kBlock];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     src = (const uint4*)staged_insts_src;
     dst = (uint4*)lds_insts;
     for (uint32_t i = tid; i < n_si * 8; i += kBlock) dst[i] = src[i];
-    if (n_sn && tid < 3) ((uint4*)&lds_consts)[tid] = ((const uint4*)staged_consts_src)[tid];
+    if (n_sn && tid < (int)(sizeof(SceneConstsDev) / 16))
+      ((uint4*)&lds_consts)[tid] = ((const uint4*)staged_consts_src)[tid];
     const uint32_t nr = n_req < kLdsReqs ? n_req : kLdsReqs;
     src = (const uint4*)reqs;
     dst = (uint4*)lds_reqs;
@@ -145,8 +149,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   uint32_t req_i = 0;
   int px = 0, py = 0;
   uint32_t s = 0, spp = 1;
-  float out_t = 0.f;
-  int out_id = -1;
 
   uint32_t mode = M_IDLE, kind = K_PRIMARY;
   Ray ray;
@@ -193,6 +195,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
   unsigned long long c_nodes = 0, c_clips = 0;
   uint32_t res_cur = 0, res_end = 0;   // this wave's reservation of job indices (wave-uniform)
+  uint32_t seen = 0;                   // queue position after this wave's last reservation
+  // the last stretch of the queue, about one chunk per wave of the grid
+  const uint32_t tail_jobs = gridDim.x * (uint32_t)kWavesPerBlock * kChunk;
 
   auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) {
     ray = r;
@@ -247,10 +252,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   // clear the accumulators for the next launch, and writes the mean.
   auto finish_sample = [&](float cr, float cg, float cb) {
     const size_t pix = (size_t)py * R->width + px;
-    if (s == 0) {
-      if (R->out_t) R->out_t[pix] = out_t;
-      if (R->out_inst) R->out_inst[pix] = out_id;
-    }
     float* o = R->out_rgb + pix * 3;
     if (spp == 1) {
       o[0] = cr;
@@ -325,8 +326,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     has_job = true;
     job_evals = 0;
     s = rem >> 6;
-    out_t = __builtin_inff();
-    out_id = -1;
     primary_ray();
   };
 
@@ -352,6 +351,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     lo_[0] = ol[0]; lo_[1] = ol[1]; lo_[2] = ol[2];
     ld_[0] = dl[0]; ld_[1] = dl[1]; ld_[2] = dl[2];
     sigma = I.sigma;
+    {
+      const bool has_cut = I.cut[0] != 0.f || I.cut[1] != 0.f || I.cut[2] != 0.f;
+      const float cx = I.cut[0] * ol[0] + I.cut[1] * ol[1] + I.cut[2] * ol[2] - I.cut[3];
+      const float cy = I.cut[0] * dl[0] + I.cut[1] * dl[1] + I.cut[2] * dl[2];
+      cut_line[tid] = make_float2(has_cut ? cx : -__builtin_inff(), cy);
+    }
     t = a0;
     t1 = a1;
     steps = 0;
@@ -482,11 +487,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     float lx = sc->light[0] - hx, ly = sc->light[1] - hy, lz = sc->light[2] - hz;
     float ll = 1.0f / __builtin_sqrtf(lx * lx + ly * ly + lz * lz);
     sh_lam = fmaxf(0.f, (nx * lx + ny * ly + nz * lz) * ll);
-    sh_ar = I.albedo[0]; sh_ag = I.albedo[1]; sh_ab = I.albedo[2];
+    const float* mat = sc->shade + 4 * cur_slot;
+    sh_ar = mat[0]; sh_ag = mat[1]; sh_ab = mat[2];
+    const float refl = mat[3];
     hpx = hx; hpy = hy; hpz = hz; hnx = nx; hny = ny; hnz = nz;
-    if (kind == K_PRIMARY) p_rho = I.refl;
+    if (kind == K_PRIMARY) p_rho = refl;
     const float off = R->shadow_offset;
-    if (kind == K_PRIMARY && R->shadows && R->bounces >= 1 && I.refl > 0.f) {
+    if (kind == K_PRIMARY && R->shadows && R->bounces >= 1 && refl > 0.f) {
       // hand the shadow ray to an idle lane and start the mirror bounce now
       tk_val[wv][0][lane] = hx + off * nx;
       tk_val[wv][1][lane] = hy + off * ny;
@@ -562,8 +569,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     switch (kind) {
       case K_PRIMARY: {
         if (s == 0) {
-          out_t = best_slot >= 0 ? limit : __builtin_inff();
-          out_id = best_slot >= 0 ? (int)best_uid : -1;
+          // depth and instance of sample 0's primary hit
+          const size_t pix = (size_t)py * R->width + px;
+          if (R->out_t) R->out_t[pix] = best_slot >= 0 ? limit : __builtin_inff();
+          if (R->out_inst) R->out_inst[pix] = best_slot >= 0 ? (int)best_uid : -1;
         }
         if (best_slot < 0) {
           finish_sample(sc->background[0], sc->background[1], sc->background[2]);
@@ -599,13 +608,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       }
       default: {  // K_HSHADOW: shade the owner's primary hit, publish it
         const int ow = help_owner;
-        const InstDev& I = *inst_ptr((int)(tk_ref[wv][ow] & 0x3fffu));
+        const float* mat = sc->shade + 4 * (tk_ref[wv][ow] & 0x3fffu);
         const float lam = tk_val[wv][3][ow];
         const float V = occluded ? 0.f : 1.f;
         const float amb = sc->ambient;
-        tk_val[wv][0][ow] = I.albedo[0] * (amb + V * lam * sc->light_rgb[0]);
-        tk_val[wv][1][ow] = I.albedo[1] * (amb + V * lam * sc->light_rgb[1]);
-        tk_val[wv][2][ow] = I.albedo[2] * (amb + V * lam * sc->light_rgb[2]);
+        tk_val[wv][0][ow] = mat[0] * (amb + V * lam * sc->light_rgb[0]);
+        tk_val[wv][1][ow] = mat[1] * (amb + V * lam * sc->light_rgb[1]);
+        tk_val[wv][2][ow] = mat[2] * (amb + V * lam * sc->light_rgb[2]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         tk_state[wv][ow] = T_DONE;
         help_owner = -1;
@@ -661,10 +670,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       const int leader = __ffsll((long long)need) - 1;
       const uint32_t n = (uint32_t)__popcll(need);
       const uint32_t have = res_end - res_cur;
+      // near the end of the queue a wave takes only the jobs it can start
+      // now, so no job waits in a busy wave's reservation while other waves
+      // run dry
+      const uint32_t take = (total_jobs - (seen < total_jobs ? seen : total_jobs)) < tail_jobs
+                                ? n - (have < n ? have : n)
+                                : kChunk;
       uint32_t nbase = 0;
       if (have < n) {
-        if (lane == leader) nbase = atomicAdd(&queue->next_job, kChunk);
+        if (lane == leader) nbase = atomicAdd(&queue->next_job, take);
         nbase = __shfl(nbase, leader);
+        seen = nbase + take;
       }
       if (!has_job && !exhausted) {
         const uint32_t rank =
@@ -678,7 +694,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       }
       if (have < n) {
         res_cur = nbase + (n - have);
-        res_end = nbase + kChunk;
+        res_end = nbase + take;
       } else {
         res_cur += n;
       }
@@ -727,9 +743,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           for (int i = 0; i < 6; ++i) kp[i] = ip->prm[i];
           const uint32_t ty = ip->type;
           int iters;
-          const double v = de_eval64(ty, nrm_pt[wv][0][owner] + (ax == 0 ? h : 0.0),
-                                     nrm_pt[wv][1][owner] + (ax == 1 ? h : 0.0),
-                                     nrm_pt[wv][2][owner] + (ax == 2 ? h : 0.0), kp, &iters);
+          const double qx = nrm_pt[wv][0][owner] + (ax == 0 ? h : 0.0);
+          const double qy = nrm_pt[wv][1][owner] + (ax == 1 ? h : 0.0);
+          const double qz = nrm_pt[wv][2][owner] + (ax == 2 ? h : 0.0);
+          double v = de_eval64(ty, qx, qy, qz, kp, &iters);
+          const float* cu = ip->cut;
+          if (cu[0] != 0.f || cu[1] != 0.f || cu[2] != 0.f) {
+            // CSG intersection with the kept half-space (NaN stays NaN)
+            const double g = (double)cu[0] * qx + (double)cu[1] * qy + (double)cu[2] * qz - (double)cu[3];
+            if (v == v) v = v > g ? v : g;
+          }
           nrm_res[wv][tap][owner] = (float)v;
           if (COUNT) {
             atomicAdd(&cnt_lds[14 + ty], 1ull);
@@ -754,10 +777,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       if (__ballot(!exhausted) == 0ull) break;
       continue;
     }
-    // waves holding long-running pixels get issue priority: the slowest
-    // pixel chains bound the frame time
-    if (__ballot(has_job && job_evals > kLongJob)) {
+    // waves holding long-running pixels get issue priority, the longer the
+    // higher: the slowest pixel chains bound the frame time
+    if (__ballot(has_job && job_evals > 4 * kLongJob)) {
+      __builtin_amdgcn_s_setprio(3);
+    } else if (__ballot(has_job && job_evals > 2 * kLongJob)) {
       __builtin_amdgcn_s_setprio(2);
+    } else if (__ballot(has_job && job_evals > kLongJob)) {
+      __builtin_amdgcn_s_setprio(1);
     } else {
       __builtin_amdgcn_s_setprio(0);
     }
@@ -770,7 +797,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float qy = lo_[1] + t * ld_[1];
         const float qz = lo_[2] + t * ld_[2];
         int iters;
-        const float de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        float de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        const float2 cl = cut_line[tid];
+        if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
         ++job_evals;
         if (COUNT) {
           atomicAdd(&cnt_lds[cur_type], 1ull);

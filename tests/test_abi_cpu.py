@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == 1
+    assert P.abi_version() == 2
     assert P.device_count() >= 0
 
 
@@ -63,6 +63,14 @@ def test_invalid_scenes_rejected_before_device(P):
     bad = W.c2_scene(); bad.geom_params = bad.geom_params.copy(); bad.geom_params[1, 4] = 0
     with pytest.raises(P.ProcrayError, match="n_iter"):
         P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.geom_cut = bad.geom_cut.copy(); bad.geom_cut[1] = (0, 0, 1, np.nan)
+    with pytest.raises(P.ProcrayError, match="non-finite cutting plane"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.geom_cut = bad.geom_cut.copy(); bad.geom_cut[1] = (1e-20, 0, 0, 0)
+    with pytest.raises(P.ProcrayError, match="normal too small"):
+        P.Scene(bad, build=False)
+    cut = W.c2_scene(); cut.geom_cut = cut.geom_cut.copy(); cut.geom_cut[1] = (0, 0, 3, 0.5)
+    P.Scene(cut, build=False).close()
 
 
 def test_render_argument_errors_before_device(P):

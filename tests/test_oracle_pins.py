@@ -19,10 +19,11 @@ from tests import analytic as AN
 EPS = 1e-4
 
 
-def _single(geom, rot=None, scale=1.0, pos=(0, 0, 0), albedo=(0.8, 0.8, 0.8), refl=0.0):
+def _single(geom, rot=None, scale=1.0, pos=(0, 0, 0), albedo=(0.8, 0.8, 0.8), refl=0.0,
+            cut=(0.0, 0.0, 0.0, 0.0)):
     b = W._SceneBuilder()
     m = b.material(albedo, refl)
-    g = b.geometry(geom)
+    g = b.geometry(geom, cut=cut)
     b.instance(g, m, W.xform(np.eye(3) if rot is None else rot, scale, pos))
     return b.build(light_pos=(2, 4, -3))
 
@@ -509,10 +510,13 @@ def test_p14_rigid_motion_and_scale_invariance():
 
 # ---------------------------------------------------------------- P15 scalar twin
 
-@pytest.mark.parametrize("which", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("which", ["c1", "c2", "c3", "cut"])
 def test_p15_scalar_twin_matches_vectorised(which):
     if which == "c1":
         wl = W.c1(8, 8)
+    elif which == "cut":
+        full = W.f1_julia_cut(10, 6)
+        wl = W.Workload("cut", [full.scenes[1]], [full.requests[1]])
     elif which == "c2":
         wl = W.c2(12, 8)
     else:
@@ -537,3 +541,134 @@ def test_p15_c2_region_scalar_twin():
     rgb, tt, ii = S.render(scene, req.camera, req.opts)
     assert np.array_equal(vec["inst"][::-1], np.array(ii))
     assert np.allclose(vec["rgb"][::-1], np.array(rgb), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P16 cutting plane (Fig. 5)
+
+def _cut_sphere_case():
+    """A rotated, scaled, translated unit sphere cut by an oblique local plane."""
+    rot = W.random_rotation(np.random.default_rng(16))
+    scale, pos = 1.7, (0.4, -0.3, 0.9)
+    n_l = np.array([1.0, 2.0, -2.0]) / 3.0
+    d_l = 0.3
+    scene = _single(W.geom_sphere(1.0), rot, scale, pos, cut=(1.0, 2.0, -2.0, 0.9))   # = (n_l, d_l) x 3
+    return scene, rot, scale, np.array(pos, np.float64), n_l, d_l
+
+
+def test_p16_cut_sphere_csg_closed_form():
+    """max(|p| - 1, n.p - d) is the CSG intersection of the ball with the kept
+    half-space: the march stops within eps/cos before the exact entry into the
+    kept solid (sphere or plane, whichever is entered last), and the normal
+    there is the sphere's or the plane's."""
+    scene, rot, scale, c, n_l, d_l = _cut_sphere_case()
+    xf = scene.inst_xform.reshape(3, 4).astype(np.float64)
+    A, b = xf[:, :3], xf[:, 3]
+    n_w = A @ n_l / np.linalg.norm(A @ n_l)
+    # look from the removed side, obliquely, so both the cut face and the
+    # remaining sphere are in view
+    u = np.cross(n_w, [0.0, 1.0, 0.0]); u /= np.linalg.norm(u)
+    eye = c + 6.0 * (0.8 * n_w + 0.6 * u)
+    cam, opts, o, d = _rays_grid(48, tuple(eye), tuple(c), fov=40.0)
+    tr, prep = _trace_closest(scene, o, d, opts)
+    # world-space closed form (A is a similarity: rotation x uniform scale)
+    R = float(np.linalg.svd(A, compute_uv=False)[0])
+    off = R * d_l                         # n_w.(p - b) <= R d_l
+    oc = o - b
+    bq = np.sum(oc * d, axis=1)
+    disc = bq * bq - (np.sum(oc * oc, axis=1) - R * R)
+    sq = np.sqrt(np.maximum(disc, 0.0))
+    s0, s1 = -bq - sq, -bq + sq
+    nd = d @ n_w
+    no = oc @ n_w
+    with np.errstate(divide="ignore"):
+        tp = (off - no) / nd
+    h0 = np.where(nd < 0, tp, -np.inf)
+    h1 = np.where(nd > 0, tp, np.inf)
+    lo_t, hi_t = np.maximum(s0, h0), np.minimum(s1, h1)
+    hit = (disc > 0) & (lo_t <= hi_t) & (hi_t > 0)
+    # stay away from silhouettes, the rim where sphere and plane meet, and grazing planes
+    margin = np.minimum(hi_t - lo_t, np.abs(s0 - h0))
+    stable = ~hit | ((margin > 2e-2) & (np.abs(nd) > 0.05))
+    stable &= np.abs(disc) > 1e-2
+    assert stable.mean() > 0.8
+    assert np.array_equal((tr["inst"] >= 0)[stable], hit[stable])
+    on_plane = hit & stable & (h0 > s0)
+    on_sphere = hit & stable & (s0 >= h0)
+    assert on_plane.sum() > 50 and on_sphere.sum() > 50
+    t_ex = lo_t
+    cos = np.where(on_plane, np.abs(nd), 1.0)
+    ps = o + s0[:, None] * d
+    cos = np.where(on_sphere, np.abs(np.sum((ps - b) / R * d, axis=1)), cos)
+    sel = on_plane | on_sphere
+    t = tr["t"][sel]
+    assert np.all(t <= t_ex[sel] + 1e-9)
+    assert np.all(t >= t_ex[sel] - EPS / cos[sel] - 1e-9)
+    # normals by central differences of the cut estimator
+    R_, K_, T0_, T1_, OL, DL = T._candidates(prep, o[sel], d[sel], np.zeros(sel.sum()),
+                                             np.full(sel.sum(), opts.tmax))
+    ol = (prep.Ainv[0] @ (o[sel] - b).T).T
+    dl = (prep.Ainv[0] @ d[sel].T).T
+    nrm = T.normals(prep, np.zeros(sel.sum(), np.int64), ol, dl, t, d[sel], 1e-3)
+    want = np.where(on_plane[sel][:, None], n_w[None, :], (o[sel] + t_ex[sel, None] * d[sel] - b) / R)
+    assert np.max(np.linalg.norm(nrm - want, axis=1)) < 2e-3
+
+
+def test_p16_cut_identities():
+    """No normal = no cut; a plane beyond the bounding sphere changes nothing;
+    the plane is scale-free in (n, d): all three render bit for bit like the
+    uncut primitive."""
+    base_scene = W.c2_scene()
+    wl = W.c2(24, 14)
+    req = wl.requests[0]
+    base = T.render(base_scene, req.camera, req.opts)
+    for cut in [(0.0, 0.0, 0.0, 0.0), (0.0, 1.0, 0.0, 50.0), (0.0, 3.0, 0.0, 150.0)]:
+        sc = W.c2_scene()
+        sc.geom_cut = np.tile(np.asarray(cut, np.float32), (len(sc.geom_type), 1))
+        out = T.render(sc, req.camera, req.opts)
+        assert np.array_equal(out["inst"], base["inst"])
+        assert np.array_equal(out["t"], base["t"])
+        assert np.array_equal(out["rgb"], base["rgb"])
+    s1 = _single(W.geom_sphere(1.0), cut=(0.0, 0.0, 1.0, 0.25))
+    s2 = _single(W.geom_sphere(1.0), cut=(0.0, 0.0, 4.0, 1.0))
+    cam, opts, o, d = _rays_grid(16, (0.5, 1.5, -4.0), (0, 0, 0))
+    a = T.render(s1, cam, opts)
+    bb = T.render(s2, cam, opts)
+    assert np.array_equal(a["t"], bb["t"]) and np.array_equal(a["rgb"], bb["rgb"])
+
+
+def test_p16_cut_face_is_flat_and_lit_by_plane_normal():
+    """Rays into the removed half of the teaser's Julia set stop on the cut
+    plane (n.p = d within eps) wherever the set's interior is exposed."""
+    wl = W.f1_julia_cut(40, 24)
+    scene, req = wl.scenes[0], wl.requests[0]
+    out = T.render(scene, req.camera, req.opts)
+    prep = T.prepare(scene)
+    hit = out["inst"] >= 0
+    assert hit.sum() > 30
+    o, d = T.camera_rays(req.camera, req.opts, np.arange(40 * 24))
+    p = o[hit] + out["t"][hit, None] * d[hit]
+    pl = np.einsum("ij,kj->ki", prep.Ainv[0], p - prep.b[0])
+    g = pl @ prep.cut[0, :3] - prep.cut[0, 3]
+    # every hit lies in the kept half-space (up to the step tolerance) ...
+    assert np.all(g <= EPS)
+    # ... and a good share of them on the plane itself: the exposed cross-section
+    assert np.mean(np.abs(g) < 2 * EPS) > 0.3
+
+
+# ---------------------------------------------------------------- P17 step-budget animation (Fig. 6)
+
+def test_p17_step_budget_animation_monotone():
+    """Frames that differ only in the ray-marching step budget: a march that
+    hits within n steps is the same march for any larger budget, so the hit
+    set grows with the budget, depth and instance stay put where they hit,
+    and every pixel that changes was flagged as budget-limited (E2)."""
+    steps = [4, 8, 16, 32, 64, 128, 256]
+    wl = W.f1_mandelbulb_anim(20, 20, steps=steps)
+    outs = [T.render(wl.scenes[0], r.camera, r.opts) for r in wl.requests]
+    for a, b in zip(outs[:-1], outs[1:]):
+        ha, hb = a["inst"] >= 0, b["inst"] >= 0
+        assert np.all(hb[ha])
+        assert np.array_equal(a["t"][ha], b["t"][ha])
+        changed = (a["inst"] != b["inst"]) | ~np.isclose(a["rgb"], b["rgb"], atol=0, rtol=0).all(axis=1)
+        assert np.all((a["excl"][changed] & T.E2_BUDGET) != 0)
+    assert (outs[0]["inst"] >= 0).sum() < (outs[-1]["inst"] >= 0).sum()

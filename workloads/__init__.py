@@ -58,6 +58,7 @@ class Scene:
     light_rgb: np.ndarray      # (3,) float32
     ambient: float
     background: np.ndarray     # (3,) float32
+    geom_cut: Optional[np.ndarray] = None   # (G, 4) float32: kept half-space n.p <= d; n = 0: none
 
     @property
     def n_inst(self) -> int:
@@ -198,7 +199,7 @@ def geom_mandelbulb(power=8, n_iter=10, bailout=2.0, half=1.2):
 
 class _SceneBuilder:
     def __init__(self):
-        self.gt, self.ga, self.gp = [], [], []
+        self.gt, self.ga, self.gp, self.gc = [], [], [], []
         self.ig, self.im, self.ix = [], [], []
         self.alb, self.refl = [], []
 
@@ -206,9 +207,9 @@ class _SceneBuilder:
         self.alb.append(albedo); self.refl.append(refl)
         return len(self.alb) - 1
 
-    def geometry(self, g) -> int:
+    def geometry(self, g, cut=(0.0, 0.0, 0.0, 0.0)) -> int:
         t, aabb, p = g
-        self.gt.append(t); self.ga.append(aabb); self.gp.append(p)
+        self.gt.append(t); self.ga.append(aabb); self.gp.append(p); self.gc.append(cut)
         return len(self.gt) - 1
 
     def instance(self, geom: int, mat: int, xf: np.ndarray):
@@ -226,6 +227,7 @@ class _SceneBuilder:
             mat_refl=_f32(self.refl).reshape(-1),
             light_pos=_f32(light_pos), light_rgb=_f32(light_rgb),
             ambient=float(np.float32(ambient)), background=_f32(background),
+            geom_cut=_f32(self.gc).reshape(-1, 4),
         )
 
 
@@ -395,6 +397,59 @@ def c5_requests(n_requests: int, rate_hz=200.0, lo=256, hi=2048, n_scenes=8,
 
 def c5(n_requests=6000, n_scenes=8) -> Workload:
     return Workload("c5_served_200rps", c5_scenes(n_scenes), c5_requests(n_requests, n_scenes=n_scenes))
+
+
+# --------------------------------------------------------------------------
+# next-step workloads: the cut Julia set and the animated Mandelbulb
+# --------------------------------------------------------------------------
+
+# Two cutting planes in the Julia set's local frame (Fig. 5 shows the set cut
+# by two different planes): the front half facing the camera removed, and an
+# oblique cut.  Stored unnormalised on purpose; the library normalises.
+F1_JULIA_CUTS = [(0.0, 0.0, -1.0, 0.0), (1.0, 1.0, -1.0, 0.15)]
+
+
+def f1_julia_cut_scene(cut) -> Scene:
+    """The teaser's Julia set alone, enlarged, cut by one plane."""
+    rng = np.random.default_rng(config_seed(2))
+    c = rng.uniform(-0.8, 0.8, 4)          # the same c as the teaser's Julia set
+    b = _SceneBuilder()
+    m = b.material(C2_ALBEDO["julia"], 0.0)
+    g = b.geometry(geom_julia(c, 12, 4.0), cut=cut)
+    b.instance(g, m, xform(np.eye(3), 1.5, (0.0, 0.0, 0.0)))
+    return b.build(light_pos=(2, 4, -3))
+
+
+def f1_julia_cut(width=320, height=180) -> Workload:
+    """One request per cutting plane, camera in front of the cut face."""
+    scenes = [f1_julia_cut_scene(c) for c in F1_JULIA_CUTS]
+    opts = RenderOpts(width, height, spp=1, jitter=0, max_steps=256, eps=1e-4, tmax=100.0,
+                      shadows=1, bounces=0)
+    reqs = [Request(i, camera((0.0, 0.8, -4.0)), opts) for i in range(len(scenes))]
+    return Workload("f1_julia_cut", scenes, reqs)
+
+
+# Ray-marching step budgets of the animation frames (Fig. 6: the Mandelbulb
+# is animated by varying the number of ray-marching iterations over time).
+F1_ANIM_STEPS = [6, 8, 11, 16, 23, 32, 45, 64, 91, 128, 181, 256]
+
+
+def f1_mandelbulb_anim_scene() -> Scene:
+    b = _SceneBuilder()
+    m = b.material(C2_ALBEDO["mandelbulb"], 0.0)
+    g = b.geometry(geom_mandelbulb(8, 10, 2.0))
+    b.instance(g, m, xform(_rot_x(-math.pi / 2), 1.5, (0.0, 0.0, 0.0)))
+    return b.build(light_pos=(2, 4, -3))
+
+
+def f1_mandelbulb_anim(width=256, height=256, steps=None) -> Workload:
+    """One request per animation frame; frame k marches at most steps[k]."""
+    steps = F1_ANIM_STEPS if steps is None else steps
+    reqs = [Request(0, camera((0.0, 1.0, -4.5)),
+                    RenderOpts(width, height, spp=1, jitter=0, max_steps=int(n), eps=1e-4,
+                               tmax=100.0, shadows=1, bounces=0))
+            for n in steps]
+    return Workload("f1_mandelbulb_animation", [f1_mandelbulb_anim_scene()], reqs)
 
 
 def pixel_sample(width: int, height: int, n: int, seed: int) -> np.ndarray:
