@@ -107,13 +107,19 @@ typedef struct { float eye[3], target[3], up[3], vfov_deg; } pr_camera;
  *  fd_h           central-difference step of the normal (world units)
  *  tile_w, tile_h wave tile shape (tile_w * tile_h == 64) or 0,0 = default
  *  step_budget    march steps between re-balancing points, 0 = default
- * The three scheduling fields never change results. */
+ *  flags          bit 0 (PR_RENDER_NATURAL_ORDER): hand out tiles in row-major
+ *                 order; by default a launch first hands out the tiles of the
+ *                 screen rectangle covered by the iterative fractals
+ *                 (Julia, Mandelbulb) of scenes with at most 256 instances,
+ *                 so their long sphere-tracing chains start early
+ * The four scheduling fields never change results. */
 typedef struct {
   uint64_t seed;
   uint32_t spp, jitter, max_steps, shadows, bounces;
   float eps, tmin, tmax, shadow_offset, fd_h;
-  uint32_t tile_w, tile_h, step_budget, reserved;
+  uint32_t tile_w, tile_h, step_budget, flags;
 } pr_render_opts;
+#define PR_RENDER_NATURAL_ORDER 1u
 
 /* BVH build options: SAH bins (4..256), maximum leaf size (1..8), traversal
  * and leaf costs; flags bit 0 (PR_BVH_HOST_ONLY) builds without uploading,

@@ -74,7 +74,7 @@ class RenderOptsC(C.Structure):
                 ("max_steps", C.c_uint32), ("shadows", C.c_uint32), ("bounces", C.c_uint32),
                 ("eps", C.c_float), ("tmin", C.c_float), ("tmax", C.c_float),
                 ("shadow_offset", C.c_float), ("fd_h", C.c_float), ("tile_w", C.c_uint32),
-                ("tile_h", C.c_uint32), ("step_budget", C.c_uint32), ("reserved", C.c_uint32)]
+                ("tile_h", C.c_uint32), ("step_budget", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class BvhOpts(C.Structure):
@@ -183,10 +183,13 @@ def camera_c(cam) -> CameraC:
                    _arr(C.c_float * 3, cam.up), float(cam.vfov_deg))
 
 
-def opts_c(o, tile=(0, 0), step_budget=0) -> RenderOptsC:
+PR_RENDER_NATURAL_ORDER = 1
+
+
+def opts_c(o, tile=(0, 0), step_budget=0, natural_order=False) -> RenderOptsC:
     return RenderOptsC(int(o.seed) & 0xFFFFFFFFFFFFFFFF, o.spp, o.jitter, o.max_steps, o.shadows,
                        o.bounces, o.eps, o.tmin, o.tmax, o.shadow_offset, o.fd_h, tile[0], tile[1],
-                       step_budget, 0)
+                       step_budget, PR_RENDER_NATURAL_ORDER if natural_order else 0)
 
 
 class Scene:
@@ -262,10 +265,10 @@ def _stream_ptr(stream):
 
 
 def render(scene: Scene, cam, opts, out_rgb, out_t=None, out_inst=None, stream=None,
-           tile=(0, 0), step_budget=0):
+           tile=(0, 0), step_budget=0, natural_order=False):
     """pr_render into caller-owned torch CUDA tensors (H, W, 3) / (H, W) / (H, W)."""
     H, W = out_rgb.shape[0], out_rgb.shape[1]
-    c, o = camera_c(cam), opts_c(opts, tile, step_budget)
+    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order)
     _check(lib().pr_render(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), _ptr(out_t),
                            _ptr(out_inst), _stream_ptr(stream)))
 

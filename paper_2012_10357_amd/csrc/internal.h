@@ -91,7 +91,8 @@ struct alignas(16) ReqDev {
   float* out_rgb;
   float* out_t;
   int32_t* out_inst;
-  uint32_t* done_counter;  // optional: per-request finished-job counter (may be null)
+  // tiles handed out first, [x0, x1) x [y0, y1) in tile units (empty: row-major order)
+  uint16_t first_x0, first_y0, first_x1, first_y1;
   unsigned long long* sample_acc;  // spp > 1: 32.32 fixed-point colour sums (W*H*3), zero between launches
   uint32_t* sample_cnt;            // spp > 1: finished samples per pixel (W*H), zero between launches
 };

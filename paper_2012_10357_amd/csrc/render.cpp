@@ -171,6 +171,7 @@ pr_status validate_opts(const pr_render_opts* o, uint32_t w, uint32_t h) {
   if (o->tile_w && (o->tile_w * o->tile_h != 64 || (64 % o->tile_w) != 0))
     return set_error(PR_ERR_INVALID_ARG, "tile_w * tile_h must be 64");
   if (o->step_budget > 4096) return set_error(PR_ERR_INVALID_ARG, "step_budget must be <= 4096");
+  if (o->flags & ~PR_RENDER_NATURAL_ORDER) return set_error(PR_ERR_INVALID_ARG, "unknown render flags");
   return PR_OK;
 }
 
@@ -186,6 +187,71 @@ pr_status check_device_ptr(const void* p, size_t bytes, const char* name, int de
   if (a.device != dev) return set_error(PR_ERR_INVALID_ARG, "%s lives on another device", name);
   (void)bytes;
   return PR_OK;
+}
+
+// Scheduling hint: the tile rectangle covering the screen projection of the
+// iterative fractals' world AABBs.  Their pixels carry the longest sphere-
+// tracing chains, which bound a frame's time once the job queue runs dry, so
+// the kernel hands these tiles out first.  Left empty (row-major order) for
+// scenes with many instances, where the rectangle would cover the screen, for
+// boxes reaching behind the camera, and on request.
+void first_region(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_render_opts* o, uint32_t w,
+                  uint32_t h, uint32_t tile_w) {
+  r.first_x0 = r.first_y0 = r.first_x1 = r.first_y1 = 0;
+  if ((o->flags & PR_RENDER_NATURAL_ORDER) || s->consts.n_inst > 256) return;
+  double f[3], up[3], rt[3], u[3], eye[3];
+  for (int i = 0; i < 3; ++i) {
+    eye[i] = cam->eye[i];
+    f[i] = (double)cam->target[i] - cam->eye[i];
+    up[i] = cam->up[i];
+  }
+  auto norm = [](double* v) {
+    const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < 3; ++i) v[i] /= l;
+  };
+  norm(f);
+  rt[0] = up[1] * f[2] - up[2] * f[1];
+  rt[1] = up[2] * f[0] - up[0] * f[2];
+  rt[2] = up[0] * f[1] - up[1] * f[0];
+  norm(rt);
+  u[0] = f[1] * rt[2] - f[2] * rt[1];
+  u[1] = f[2] * rt[0] - f[0] * rt[2];
+  u[2] = f[0] * rt[1] - f[1] * rt[0];
+  const double sh = std::tan((double)cam->vfov_deg * M_PI / 360.0), aspect = (double)w / h;
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  bool any = false;
+  for (uint32_t i = 0; i < s->consts.n_inst; ++i) {
+    const uint32_t ty = s->host_insts[i].type;
+    if (ty != PR_JULIA && ty != PR_MANDELBULB) continue;
+    any = true;
+    const float* b = &s->world_aabb[6 * (size_t)i];
+    for (int c = 0; c < 8; ++c) {
+      const double p[3] = {(c & 1) ? b[3] : b[0], (c & 2) ? b[4] : b[1], (c & 4) ? b[5] : b[2]};
+      const double v[3] = {p[0] - eye[0], p[1] - eye[1], p[2] - eye[2]};
+      const double z = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+      if (!(z > 1e-6)) return;   // reaches behind the camera: keep row-major order
+      const double sx = (v[0] * rt[0] + v[1] * rt[1] + v[2] * rt[2]) / z / (sh * aspect);
+      const double sy = (v[0] * u[0] + v[1] * u[1] + v[2] * u[2]) / z / sh;
+      const double px = (sx + 1.0) * 0.5 * w, py = (1.0 - sy) * 0.5 * h;
+      x0 = std::min(x0, px);
+      x1 = std::max(x1, px);
+      y0 = std::min(y0, py);
+      y1 = std::max(y1, py);
+    }
+  }
+  if (!any) return;
+  const uint32_t th = 64 / tile_w, tiles_y = (h + th - 1) / th;
+  auto clampi = [](double v, uint32_t hi) -> uint32_t {
+    return v <= 0.0 ? 0u : (v >= (double)hi ? hi : (uint32_t)v);
+  };
+  const uint32_t tx0 = clampi(std::floor(x0 / tile_w), r.tiles_x), tx1 = clampi(std::ceil(x1 / tile_w), r.tiles_x);
+  const uint32_t ty0 = clampi(std::floor(y0 / th), tiles_y), ty1 = clampi(std::ceil(y1 / th), tiles_y);
+  if (tx0 >= tx1 || ty0 >= ty1) return;
+  if (tx0 == 0 && ty0 == 0 && tx1 == r.tiles_x && ty1 == tiles_y) return;   // the whole frame
+  r.first_x0 = (uint16_t)tx0;
+  r.first_y0 = (uint16_t)ty0;
+  r.first_x1 = (uint16_t)tx1;
+  r.first_y1 = (uint16_t)ty1;
 }
 
 void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_render_opts* o, uint32_t w,
@@ -224,7 +290,7 @@ void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_rende
   r.out_rgb = rgb;
   r.out_t = t;
   r.out_inst = inst;
-  r.done_counter = nullptr;
+  first_region(r, s, cam, o, w, h, tile_w);
 }
 
 int g_blocks_per_cu = 0;

@@ -83,6 +83,39 @@ __device__ __forceinline__ bool local_slab(const float o[3], const float d[3], c
   return !empty && t0 <= t1;
 }
 
+// The q-th tile a request hands out: first the tiles of its rectangle
+// [x0, x1) x [y0, y1) in row-major order, then every other tile in row-major
+// order (rows above, the parts of the rectangle's rows left and right of it,
+// rows below).  A bijection on [0, tiles_x * tiles_y); an empty rectangle
+// gives plain row-major order.
+__device__ __forceinline__ void tile_at(const ReqDev* R, uint32_t q, uint32_t& tx, uint32_t& ty) {
+  const uint32_t nx = R->tiles_x;
+  const uint32_t x0 = R->first_x0, x1 = R->first_x1, y0 = R->first_y0, y1 = R->first_y1;
+  const uint32_t w = x1 - x0, h = y1 - y0;
+  if (q < w * h) {
+    ty = y0 + q / w;
+    tx = x0 + q % w;
+    return;
+  }
+  q -= w * h;
+  if (q < y0 * nx) {
+    ty = q / nx;
+    tx = q % nx;
+    return;
+  }
+  q -= y0 * nx;
+  const uint32_t side = nx - w;   // tiles of a rectangle row outside the rectangle
+  if (q < h * side) {
+    ty = y0 + q / side;
+    const uint32_t c = q % side;
+    tx = c < x0 ? c : c + w;
+    return;
+  }
+  q -= h * side;
+  ty = y1 + q / nx;
+  tx = q % nx;
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(const ReqDev* __restrict__ reqs,
                                                        QueueDev* __restrict__ queue,
@@ -276,7 +309,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         atomicExch(&R->sample_cnt[pix], 0u);
       }
     }
-    if (R->done_counter) atomicAdd(R->done_counter, 1u);
     has_job = false;
     mode = M_IDLE;
   };
@@ -310,15 +342,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     bind_request(a);
     uint32_t local = j - R->job_begin;
     const uint32_t per_tile = 64u * spp;
-    uint32_t tile = local / per_tile, rem = local - tile * per_tile;
+    const uint32_t q = local / per_tile, rem = local - q * per_tile;
     uint32_t li = rem & 63u;
     uint32_t tw = R->tile_w, th = 64u / tw;
-    uint32_t tx = tile % R->tiles_x, ty = tile / R->tiles_x;
+    uint32_t tx, ty;
+    tile_at(R, q, tx, ty);
     px = (int)(tx * tw + li % tw);
     py = (int)(ty * th + li / tw);
     if (px >= (int)R->width || py >= (int)R->height) {
-      // ragged tile edge: nothing to render, counts as done
-      if (R->done_counter) atomicAdd(R->done_counter, 1u);
+      // ragged tile edge: nothing to render
       has_job = false;
       mode = M_IDLE;
       return;

@@ -96,6 +96,11 @@ def test_render_argument_errors_before_device(P):
         P.render(sc, cam, o, big)
     with pytest.raises(P.ProcrayError, match="tile"):
         P.render(sc, cam, o, fake, tile=(8, 4))
+    import ctypes as C
+    oc = P.opts_c(o)
+    oc.flags = 2
+    st = P.lib().pr_render(sc.handle, C.byref(P.camera_c(cam)), C.byref(oc), 64, 64, None, None, None, None)
+    assert st == P.PR_ERR_INVALID_ARG and b"flags" in P.lib().pr_last_error()
     # host-only build: not uploaded, so rendering is refused before any device call
     with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
         P.render(sc, cam, o, fake)

@@ -30,6 +30,34 @@ def test_tile_and_budget_invariance():
             _eq(ref, gpu_render(P, sc, req.camera, req.opts, tile=tile, step_budget=budget))
 
 
+@pytest.mark.parametrize("case", ["teaser 320x180", "teaser 61x37", "teaser 1x97", "teaser 130x1",
+                                  "close-up", "fractal behind", "tile 64x1"])
+def test_first_region_order_is_invisible(case):
+    """Handing out the fractals' screen rectangle first (the default) and
+    plain row-major order give the same bits, with every pixel written."""
+    P = require_gpu()
+    desc = W.c2_scene()
+    sc = P.Scene(desc)
+    tile = (0, 0)
+    if case.startswith("teaser"):
+        w, h = (int(v) for v in case.split()[1].split("x"))
+        cam, opts = W.c2_camera(), W.c2_opts(w, h)
+    elif case == "close-up":          # the Mandelbulb's box overfills the frame
+        cam, opts = W.camera((0.9, 0.6, -2.4), (0.9, 0.1, -0.9)), W.c2_opts(200, 120)
+    elif case == "fractal behind":    # box corners behind the eye: row-major order
+        cam, opts = W.camera((0.9, 0.1, -1.2), (0.9, 0.1, -5.0)), W.c2_opts(96, 64)
+    else:
+        cam, opts, tile = W.c2_camera(), W.c2_opts(257, 75), (64, 1)
+    a = gpu_render(P, sc, cam, opts, tile=tile)
+    rgb, t, inst = alloc(opts.width, opts.height)
+    P.render(sc, cam, opts, rgb, t, inst, tile=tile, natural_order=True)
+    import torch
+    torch.cuda.synchronize()
+    b = (rgb.cpu().numpy(), t.cpu().numpy(), inst.cpu().numpy())
+    assert np.isfinite(a[0]).all() and (a[2] >= -1).all()
+    _eq(a, b)
+
+
 def test_bvh_option_invariance():
     P = require_gpu()
     desc = W.random_instances_scene(np.random.default_rng(3), 300, W.C3_KINDS)
