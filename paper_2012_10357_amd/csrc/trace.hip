@@ -83,8 +83,15 @@ __device__ __forceinline__ bool local_slab(const float o[3], const float d[3], c
   return !empty && t0 <= t1;
 }
 
+// k-th of n indices visited from the middle outwards: m, m+1, m-1, m+2, ...
+__device__ __forceinline__ uint32_t centre_out(uint32_t k, uint32_t n) {
+  const uint32_t m = (n - 1) / 2;
+  return k == 0 ? m : ((k & 1u) ? m + (k + 1) / 2 : m - k / 2);
+}
+
 // The q-th tile a request hands out: first the tiles of its rectangle
-// [x0, x1) x [y0, y1) in row-major order, then every other tile in row-major
+// [x0, x1) x [y0, y1), rows and columns each from the middle outwards (the
+// fractal bodies sit in the middle), then every other tile in row-major
 // order (rows above, the parts of the rectangle's rows left and right of it,
 // rows below).  A bijection on [0, tiles_x * tiles_y); an empty rectangle
 // gives plain row-major order.
@@ -93,8 +100,8 @@ __device__ __forceinline__ void tile_at(const ReqDev* R, uint32_t q, uint32_t& t
   const uint32_t x0 = R->first_x0, x1 = R->first_x1, y0 = R->first_y0, y1 = R->first_y1;
   const uint32_t w = x1 - x0, h = y1 - y0;
   if (q < w * h) {
-    ty = y0 + q / w;
-    tx = x0 + q % w;
+    ty = y0 + centre_out(q / w, h);
+    tx = x0 + centre_out(q % w, w);
     return;
   }
   q -= w * h;
