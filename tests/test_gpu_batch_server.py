@@ -69,7 +69,11 @@ def test_bvh_option_invariance():
 
 
 def _c4_small(n=24):
+    """Small batched requests over the teaser scene; every other one with the
+    mirror bounce (and so with shadow rays handed between lanes)."""
     wl = W.c4(n_requests=n, lo=64, hi=320)
+    for i, r in enumerate(wl.requests):
+        r.opts.bounces = i % 2
     return wl
 
 
@@ -144,6 +148,7 @@ def test_server_mix_equals_alone():
     for i, r in enumerate(reqs):
         if r.scene_index == 0:
             r.camera = W.camera((1.0 * (i % 3), 1.5, -6.0))
+            r.opts.bounces = 1
         tickets.append(srv.submit(dev[r.scene_index], r.camera, r.opts, tag=i))
     for tk, r in zip(tickets, reqs):
         res = srv.wait(tk, 60000)
@@ -156,6 +161,16 @@ def test_server_mix_equals_alone():
     st = srv.stats()
     assert st.completed == 24 and st.pool_bytes_in_use == 0
     srv.close()
+
+
+def test_launch_shape_keeps_three_workgroups_per_cu():
+    """The kernel's registers and LDS must leave room for three 256-thread
+    workgroups per compute unit (12 waves): the grid is sized from this, and
+    one workgroup fewer costs about a third of the throughput of dense scenes."""
+    P = require_gpu()
+    cus, wg = P.launch_shape()
+    assert cus >= 1
+    assert wg == 3, (cus, wg)
 
 
 def test_counts_match_oracle_work():
