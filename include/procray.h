@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 2
+#define PR_ABI_VERSION 3
 
 typedef enum {
   PR_OK = 0,
@@ -150,6 +150,26 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom,
                           const pr_instance* insts, uint32_t n_inst,
                           const pr_material* mats, uint32_t n_mat,
                           const pr_scene_consts* consts, pr_scene** out);
+
+/* Adds a triangle mesh (Sec. 4.1, listing "Triangle geometry creation":
+ * vertex and index arrays plus an instance vector; the paper's sample scene
+ * has a triangle plane, Fig. 4) to a scene before pr_bvh_build.
+ *  vertices   host, n_vertices x 3 float (local xyz)
+ *  indices    host, n_triangles x 3 uint32, each < n_vertices
+ *  instances  host, n_instances placements: material index and row-major
+ *             3x4 local-to-world transform (the geometry field is ignored)
+ * Triangles are double-sided and intersected in closed form.  Every
+ * (instance, triangle) pair becomes one leaf item of the scene's BVH, in
+ * world space; hits on it report the id n_proc + k in out_inst, where
+ * n_proc counts the procedural instances of pr_scene_create and k numbers
+ * the pairs instance-major across all added meshes.  Validation: finite
+ * vertices and transforms (|det A| > 1e-12), indices and materials in
+ * range, no degenerate (zero-area) triangle after the transform, at most
+ * 16384 items per scene in total.  Clears a previous build; PR_ERR_BUSY
+ * while renders of the scene may be in flight. */
+pr_status pr_scene_add_mesh(pr_scene* scene, const float* vertices, uint32_t n_vertices,
+                            const uint32_t* indices, uint32_t n_triangles,
+                            const pr_instance* instances, uint32_t n_instances);
 
 /* Builds a binned-SAH BVH over the instances' world AABBs (the TLAS of
  * Sec. 2.2.3 / Sec. 3.1; each geometry's BLAS is its single AABB) on the

@@ -10,7 +10,9 @@ vectorisation slip in either shows up as a disagreement:
 * the box-frame is the minimum over all 12 explicit edge bars (no folding);
 * the wedge distance of the pac-man is computed from the two boundary
   half-lines explicitly;
-* quaternion products are written out component by component.
+* quaternion products are written out component by component;
+* triangles are intersected with the Moeller-Trumbore formulation instead
+  of the plane equation and signed areas.
 
 Same definitions otherwise (pinhole camera, local-space slab clip, sphere
 tracing v = sigma DE, eps stop, central-difference normal, Lambert with a
@@ -143,6 +145,23 @@ class ScalarScene:
                 Ainv=Ainv, b=b, sigma=sigma, lo=aabb[0:3], hi=aabb[3:6],
                 gt=int(scene.geom_type[g]), prm=[float(v) for v in scene.geom_params[g]],
                 albedo=[float(v) for v in scene.mat_albedo[m]], refl=float(scene.mat_refl[m])))
+        # mesh triangles in world space (float64 placement), ids after the instances
+        self.tri = []
+        n_proc = len(self.inst)
+        for mesh in (getattr(scene, "meshes", None) or []):
+            verts = [tuple(float(c) for c in v) for v in mesh["vertices"]]
+            for mat, xf in zip(mesh["inst_mat"], mesh["inst_xform"]):
+                x = [float(c) for c in xf]
+                def place(p):
+                    return tuple(x[4 * r] * p[0] + x[4 * r + 1] * p[1] + x[4 * r + 2] * p[2] + x[4 * r + 3]
+                                 for r in range(3))
+                for f in mesh["indices"]:
+                    a, b_, c = (place(verts[int(i)]) for i in f)
+                    e1, e2 = _sub(b_, a), _sub(c, a)
+                    self.tri.append(dict(v0=a, e1=e1, e2=e2, n=_nrm(_cross(e1, e2)),
+                                         albedo=[float(v) for v in scene.mat_albedo[int(mat)]],
+                                         refl=float(scene.mat_refl[int(mat)]),
+                                         id=n_proc + len(self.tri)))
         self.light = tuple(float(v) for v in scene.light_pos)
         self.light_rgb = tuple(float(v) for v in scene.light_rgb)
         self.ambient = float(scene.ambient)
@@ -198,6 +217,25 @@ def _march(ins, ol, dl, t0, t1, n_max, eps):
     return None
 
 
+def _tri_hit(tr, o, d, tmin, tmax):
+    """Moeller-Trumbore: distance of the ray's hit on the triangle (both
+    sides, closed edges) inside [tmin, tmax], or None."""
+    p = _cross(d, tr["e2"])
+    det = _dot(tr["e1"], p)
+    if det == 0.0:
+        return None
+    s = _sub(o, tr["v0"])
+    u = _dot(s, p) / det
+    if u < 0.0 or u > 1.0:
+        return None
+    q = _cross(s, tr["e1"])
+    v = _dot(d, q) / det
+    if v < 0.0 or u + v > 1.0:
+        return None
+    t = _dot(tr["e2"], q) / det
+    return t if tmin <= t <= tmax else None
+
+
 def trace_closest(sc, o, d, tmin, tmax, opts):
     best_t, best_k = INF, -1
     for k, ins in enumerate(sc.inst):
@@ -210,6 +248,10 @@ def trace_closest(sc, o, d, tmin, tmax, opts):
         th = _march(ins, ol, dl, iv[0], iv[1], opts.max_steps, opts.eps)
         if th is not None and (th < best_t or (th == best_t and k < best_k)):
             best_t, best_k = th, k
+    for tr in sc.tri:
+        th = _tri_hit(tr, o, d, tmin, min(tmax, best_t))
+        if th is not None and (th < best_t or (th == best_t and tr["id"] < best_k)):
+            best_t, best_k = th, tr["id"]
     return best_t, best_k
 
 
@@ -222,7 +264,7 @@ def trace_any(sc, o, d, tmax, opts):
             continue
         if _march(ins, ol, dl, iv[0], iv[1], opts.max_steps, opts.eps) is not None:
             return True
-    return False
+    return any(_tri_hit(tr, o, d, 0.0, tmax) is not None for tr in sc.tri)
 
 
 def _normal(ins, o, d, t, h_fd):
@@ -239,9 +281,16 @@ def _normal(ins, o, d, t, h_fd):
     return _mul(d, -1.0) if not ln > 0 else _mul(nw, 1.0 / ln)
 
 
+def _item(sc, k):
+    return sc.inst[k] if k < len(sc.inst) else sc.tri[k - len(sc.inst)]
+
+
 def _shade(sc, o, d, t, k, opts):
-    ins = sc.inst[k]
-    n = _normal(ins, o, d, t, opts.fd_h)
+    ins = _item(sc, k)
+    if k < len(sc.inst):
+        n = _normal(ins, o, d, t, opts.fd_h)
+    else:
+        n = ins["n"] if _dot(ins["n"], d) <= 0.0 else _mul(ins["n"], -1.0)
     p = _add(o, _mul(d, t))
     V = 1.0
     if opts.shadows:
@@ -282,7 +331,7 @@ def render(scene, cam, opts):
                 c = sc.bg
             else:
                 c, n, p = _shade(sc, eye, d, t, k, opts)
-                rho = sc.inst[k]["refl"]
+                rho = _item(sc, k)["refl"]
                 if opts.bounces >= 1 and rho > 0:
                     dn = _dot(d, n)
                     rd = _sub(d, _mul(n, 2.0 * dn))

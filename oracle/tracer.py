@@ -3,9 +3,8 @@
 The render follows the per-ray pipeline of the paper's Sec. 2.2.3 and
 Sec. 4.1 in this order:
 
-1. ray generation: a pinhole camera ray through each pixel (the ray
-   generation shader "starts at the camera position and goes through a
-   pixel");
+1. ray generation: a pinhole camera ray from the eye through each pixel
+   (the ray-generation shader's role);
 2. candidate search: every instance's local AABB is slab-tested in the
    instance's local space (Sec. 4.1: the transforms live in an instance
    buffer so intersection works in local space).  Brute force over all
@@ -21,6 +20,13 @@ Sec. 4.1 in this order:
    group creation", so a shadow ray is occluded when *any* instance reports
    a hit) and an optional mirror bounce shaded the same way;
 6. miss: the background colour (the radiance miss shader).
+
+Triangle meshes (Sec. 4.1, listing "Triangle geometry creation"; the plane
+of the sample scene, Fig. 4) are placed by their instance transforms in
+float64 and intersected in closed form -- the plane equation and signed-area
+barycentric coordinates, both sides of a triangle -- against every ray;
+their hits join the same lexicographic closest-hit rule, with ids following
+the procedural instances.
 
 Readings of points the paper leaves open are listed in the project's design
 notes; the ones that fix arithmetic are restated where they are used below.
@@ -44,7 +50,14 @@ import numpy as np
 from .de import de_eval, JULIA, MANDELBULB
 
 HIT, MISS_EXIT, MISS_BUDGET, MISS_NAN = 0, 1, 2, 3
-E1_GRAZE, E2_BUDGET, E3_MARGINAL, E4_NORMAL = 1, 2, 4, 8
+E1_GRAZE, E2_BUDGET, E3_MARGINAL, E4_NORMAL, E5_TRIANGLE = 1, 2, 4, 8, 16
+# E5: a triangle decision float32 may take differently -- the ray passes
+# within 1e-5 (barycentric) of a triangle's edge, meets its plane at a
+# grazing angle (|n.d| < 1e-3), or hits a triangle and a procedural surface
+# at distances within 1e-5 relative of each other.
+TRI_EDGE = 1e-5
+TRI_GRAZE = 1e-3
+TRI_TIE = 1e-5
 GRAZE_V = 1e-3
 # E4: displacement of the hit point (relative to t) at which the normal's
 # conditioning is probed -- about four float32 ulps of the hit distance --
@@ -90,8 +103,11 @@ class Prepared:
     gtype: np.ndarray    # (N,)
     prm: np.ndarray      # (N, 8)
     cut: np.ndarray      # (N, 4): unit normal n and offset d of the kept half-space n.p <= d; zeros = none
-    albedo: np.ndarray   # (N, 3)
-    refl: np.ndarray     # (N,)
+    albedo: np.ndarray   # (N + T, 3): procedural instances, then triangles
+    refl: np.ndarray     # (N + T,)
+    tri: np.ndarray      # (T, 3, 3) world-space triangle vertices
+    tri_n: np.ndarray    # (T, 3) unit face normals
+    n_proc: int          # N: triangle j reports id N + j
     light: np.ndarray
     light_rgb: np.ndarray
     ambient: float
@@ -123,6 +139,54 @@ def apply_cut(v, pts, cut):
     return np.where(on, np.maximum(v, g), v)
 
 
+def mesh_triangles(scene):
+    """World-space triangles of the scene's meshes, instance-major (every
+    placement of a mesh, then its triangles in index order), and their
+    material indices.  Vertices are placed in float64: v_w = A v + b."""
+    tris, mats = [], []
+    for mesh in (getattr(scene, "meshes", None) or []):
+        v = np.asarray(mesh["vertices"], np.float64).reshape(-1, 3)
+        f = np.asarray(mesh["indices"], np.int64).reshape(-1, 3)
+        xf = np.asarray(mesh["inst_xform"], np.float64).reshape(-1, 3, 4)
+        for mat, x in zip(np.asarray(mesh["inst_mat"], np.int64).reshape(-1), xf):
+            w = v @ x[:, :3].T + x[:, 3]
+            tris.append(w[f])
+            mats.append(np.full(f.shape[0], mat, np.int64))
+    if not tris:
+        return np.zeros((0, 3, 3)), np.zeros(0, np.int64)
+    return np.concatenate(tris), np.concatenate(mats)
+
+
+def triangle_hits(prep, o, d, tmin, tmax):
+    """Every ray against every triangle: the ray meets the triangle's plane
+    at t = n.(v0 - o) / n.d and hits when the signed-area barycentric
+    coordinates of that point are all >= 0 and t lies in [tmin, tmax].
+
+    Returns the hit distance t (m, T) (+inf where no hit), the plane
+    distance (m, T) whether or not the point is inside, the smallest
+    barycentric coordinate of the plane point (m, T) and |n.d| (m, T)."""
+    m, T = o.shape[0], prep.tri.shape[0]
+    if T == 0:
+        z = np.zeros((m, 0))
+        return z + np.inf, z + np.inf, z, z
+    n = prep.tri_n
+    v0, v1, v2 = prep.tri[:, 0], prep.tri[:, 1], prep.tri[:, 2]
+    nd = d @ n.T
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = (np.sum(v0 * n, axis=1)[None, :] - o @ n.T) / nd
+    p = o[:, None, :] + t[..., None] * d[:, None, :]
+    area = np.sum(np.cross(v1 - v0, v2 - v0) * n, axis=1)          # twice the area
+    lam = [np.sum(np.cross(b[None] - p, c[None] - p) * n[None], axis=2) / area[None]
+           for b, c in ((v1, v2), (v2, v0), (v0, v1))]
+    bmin = np.minimum(np.minimum(lam[0], lam[1]), lam[2])
+    tmin = np.broadcast_to(np.asarray(tmin, np.float64), (m,))[:, None]
+    tmax = np.broadcast_to(np.asarray(tmax, np.float64), (m,))[:, None]
+    ok = (nd != 0.0) & (bmin >= 0.0) & (t >= tmin) & (t <= tmax)
+    bmin = np.where(np.isfinite(bmin), bmin, np.inf)
+    t_plane = np.where(np.isfinite(t), t, np.inf)
+    return np.where(ok, t, np.inf), t_plane, bmin, np.abs(nd)
+
+
 def prepare(scene) -> Prepared:
     """Per-instance local frames from the float32 scene, upcast to float64.
 
@@ -139,13 +203,20 @@ def prepare(scene) -> Prepared:
     g = np.asarray(scene.inst_geom, np.int64)
     aabb = np.asarray(scene.geom_aabb, np.float64)[g]
     mat = np.asarray(scene.inst_mat, np.int64)
+    tri, tri_mat = mesh_triangles(scene)
+    e1, e2 = tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]
+    nrm = np.cross(e1, e2)
+    tri_n = nrm / np.maximum(np.linalg.norm(nrm, axis=1), 1e-300)[:, None]
+    alb = np.asarray(scene.mat_albedo, np.float64)
+    rfl = np.asarray(scene.mat_refl, np.float64)
     return Prepared(
         A=A, b=b, Ainv=Ainv, sigma=sigma, lo=aabb[:, 0:3], hi=aabb[:, 3:6],
         gtype=np.asarray(scene.geom_type, np.int64)[g],
         prm=np.asarray(scene.geom_params, np.float64)[g],
         cut=unit_cuts(scene)[g],
-        albedo=np.asarray(scene.mat_albedo, np.float64)[mat],
-        refl=np.asarray(scene.mat_refl, np.float64)[mat],
+        albedo=np.concatenate([alb[mat], alb[tri_mat]]),
+        refl=np.concatenate([rfl[mat], rfl[tri_mat]]),
+        tri=tri, tri_n=tri_n, n_proc=int(g.shape[0]),
         light=np.asarray(scene.light_pos, np.float64),
         light_rgb=np.asarray(scene.light_rgb, np.float64),
         ambient=float(scene.ambient),
@@ -382,6 +453,24 @@ def trace(prep, o, d, tmin, tmax, opts, mode, source=None, counts=None):
             t_best[R[hp]] = res["thit"][hp]
             inst[R[hp]] = K[hp]
             win[R[hp]] = hp
+        # triangles: the nearest triangle hit wins over a procedural hit only
+        # when strictly nearer (its id, n_proc + j, is larger)
+        tt, tpl, bmin, cosd = triangle_hits(prep, o, d, tmin, tmax)
+        if tt.shape[1]:
+            j = np.argmin(tt, axis=1)
+            rows = np.arange(m)
+            t_tri = tt[rows, j]
+            better = np.isfinite(t_tri) & (t_tri < t_best)
+            both = np.isfinite(t_tri) & np.isfinite(t_best)
+            gap = np.abs(np.where(both, t_tri, 0.0) - np.where(both, t_best, 0.0))
+            tie = both & (gap <= TRI_TIE * np.maximum(1.0, np.where(both, np.minimum(t_tri, t_best), 0.0)))
+            t_best = np.where(better, t_tri, t_best)
+            inst = np.where(better, prep.n_proc + j, inst)
+            win = np.where(better, -1, win)
+            t_lim = np.where(np.isfinite(t_best), t_best, tmax)
+            edge = (np.abs(bmin) < TRI_EDGE) & (tpl >= tmin[:, None]) & (tpl <= t_lim[:, None] * (1 + TRI_TIE))
+            graze = better & (cosd[rows, j] < TRI_GRAZE)
+            excl |= np.where(edge.any(axis=1) | graze | tie, E5_TRIANGLE, 0)
         t_lim_ray = np.where(np.isfinite(t_best), t_best, tmax)
         for gt, (sel, h) in hist.items():
             e1, e2, e3, rel_mask = _pair_flags(h["T"], h["V"], h["n"], h["out"],
@@ -406,6 +495,14 @@ def trace(prep, o, d, tmin, tmax, opts, mode, source=None, counts=None):
         np.logical_or.at(flagged, R[sel], e1 | e2 | e3)
         bits = e1 * E1_GRAZE | e2 * E2_BUDGET | e3 * E3_MARGINAL
         np.bitwise_or.at(excl, R[sel], bits.astype(np.int64))
+    tt, tpl, bmin, cosd = triangle_hits(prep, o, d, tmin, tmax)
+    if tt.shape[1]:
+        th = np.isfinite(tt)
+        occluded |= th.any(axis=1)
+        robust |= (th & (np.abs(bmin) >= TRI_EDGE) & (cosd >= TRI_GRAZE)).any(axis=1)
+        edge = (np.abs(bmin) < TRI_EDGE) & (tpl >= tmin[:, None]) & (tpl <= tmax[:, None])
+        e5 = edge.any(axis=1) | (th & (cosd < TRI_GRAZE)).any(axis=1)
+        excl |= np.where(e5, E5_TRIANGLE, 0)
     excl = np.where(robust, 0, excl)
     if counts is not None:
         _count_canonical(prep, R, K, T0, res, hist, m, "any", counts)
@@ -520,14 +617,24 @@ def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow, extra_shift=None):
     if hidx.size == 0:
         return col, excl, nrm, pw, hit, sens
     R, K, OL, DL = tr["pairs"]
-    wp = tr["win"][hidx]
     inst = tr["inst"][hidx]
     t = tr["t"][hidx]
-    n = normals(prep, inst, OL[wp], DL[wp], t, d[hidx], float(opts.fd_h), counts)
-    shift = E4_REL_SHIFT * np.maximum(t, 1.0)
-    if extra_shift is not None:
-        shift = np.maximum(shift, extra_shift[hidx])
-    dn = normal_sensitivity(prep, inst, OL[wp], DL[wp], t, d[hidx], float(opts.fd_h), shift)
+    n = np.zeros((hidx.size, 3))
+    dn = np.zeros(hidx.size)
+    proc = inst < prep.n_proc
+    if proc.any():
+        wp = tr["win"][hidx[proc]]
+        ip, tp = inst[proc], t[proc]
+        n[proc] = normals(prep, ip, OL[wp], DL[wp], tp, d[hidx[proc]], float(opts.fd_h), counts)
+        shift = E4_REL_SHIFT * np.maximum(tp, 1.0)
+        if extra_shift is not None:
+            shift = np.maximum(shift, extra_shift[hidx[proc]])
+        dn[proc] = normal_sensitivity(prep, ip, OL[wp], DL[wp], tp, d[hidx[proc]], float(opts.fd_h), shift)
+    if (~proc).any():
+        # triangles are double-sided: the face normal turned toward the ray
+        fn = prep.tri_n[inst[~proc] - prep.n_proc]
+        side = np.where(np.sum(fn * d[hidx[~proc]], axis=1) > 0.0, -1.0, 1.0)
+        n[~proc] = fn * side[:, None]
     excl[hidx] |= np.where(dn > E4_MAX_DN, E4_NORMAL, 0)
     sens[hidx] = dn
     p = o[hidx] + t[:, None] * d[hidx]

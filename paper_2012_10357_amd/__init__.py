@@ -27,7 +27,7 @@ PR_BVH_HOST_ONLY = 1
 
 # every symbol the header declares
 EXPORTS = [
-    "pr_scene_create", "pr_bvh_build", "pr_scene_bvh_export", "pr_scene_device_bytes",
+    "pr_scene_create", "pr_scene_add_mesh", "pr_bvh_build", "pr_scene_bvh_export", "pr_scene_device_bytes",
     "pr_scene_destroy", "pr_render", "pr_render_counts", "pr_render_batch", "pr_autotune",
     "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
@@ -137,6 +137,7 @@ def lib():
     sig = {
         "pr_scene_create": [P, U32, P, U32, P, U32, P, C.POINTER(C.c_void_p)],
         "pr_bvh_build": [P, P],
+        "pr_scene_add_mesh": [P, P, U32, P, U32, P, U32],
         "pr_scene_bvh_export": [P, P, U32, P, U32, C.POINTER(U32), C.POINTER(U32)],
         "pr_scene_device_bytes": [P, C.POINTER(U64)],
         "pr_scene_destroy": [P],
@@ -224,8 +225,30 @@ class Scene:
         _check(L.pr_scene_create(geoms, G, insts, N, mats, M, C.byref(consts), C.byref(h)))
         self.handle = h
         self.n_inst = N
+        for mesh in (getattr(desc, "meshes", None) or []):
+            try:
+                self.add_mesh(mesh["vertices"], mesh["indices"], mesh["inst_mat"], mesh["inst_xform"])
+            except ProcrayError:
+                self.close()
+                raise
         if build:
             self.build(bvh)
+
+    def add_mesh(self, vertices, indices, inst_mat, inst_xform):
+        """pr_scene_add_mesh: vertices (V, 3), indices (F, 3), one placement per
+        entry of inst_mat / inst_xform (K,), (K, 12); clears the build."""
+        v = np.ascontiguousarray(vertices, np.float32).reshape(-1, 3)
+        f = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
+        mats = np.asarray(inst_mat).reshape(-1)
+        xf = np.asarray(inst_xform, np.float32).reshape(-1, 12)
+        K = len(mats)
+        insts = (Instance * K)()
+        for i in range(K):
+            insts[i].geometry = 0
+            insts[i].material = int(mats[i])
+            insts[i].xform = _arr(C.c_float * 12, xf[i])
+        _check(lib().pr_scene_add_mesh(self.handle, v.ctypes.data_as(C.c_void_p), len(v),
+                                       f.ctypes.data_as(C.c_void_p), len(f), insts, K))
 
     def build(self, bvh: Optional[BvhOpts] = None):
         _check(lib().pr_bvh_build(self.handle, C.byref(bvh) if bvh is not None else None))

@@ -49,6 +49,8 @@ void release_ctx(LaunchCtx* c);
 struct pr_scene {
   std::vector<pr::InstDev> host_insts;   // user order
   std::vector<float> host_shade;         // user order: albedo rgb, reflectivity
+  std::vector<pr_material> mats;         // the scene's materials (for meshes added later)
+  uint32_t n_proc = 0;                   // procedural instances; triangle items follow
   std::vector<float> world_aabb;         // 6 per instance
   std::vector<pr::HostNode> nodes;       // BVH, children adjacent, breadth-first
   std::vector<pr::NodeDev> dnodes;       // device layout: child boxes in the parent

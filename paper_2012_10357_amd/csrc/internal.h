@@ -16,7 +16,12 @@ constexpr int kStackDepth = 32;       // BVH traversal stack entries per lane
 constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kBlock = 256;           // threads per workgroup (4 waves)
 
+// Type tag of a triangle leaf item (not a procedural type).
+constexpr uint32_t kTriangle = PR_NUM_TYPES;
+
 // Per-instance record, 32 words.  Local point = Ainv * (world - b).
+// A triangle item reuses it in world space: Ainv = (v0, e1 = v1 - v0,
+// e2 = v2 - v0), b = unit face normal, lo/hi = its world AABB, type = kTriangle.
 struct alignas(16) InstDev {
   float Ainv[9];
   float b[3];

@@ -505,6 +505,8 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
     }
     s->consts.ambient = consts->ambient;
     s->consts.n_inst = n_inst;
+    s->n_proc = n_inst;
+    s->mats.assign(mats, mats + n_mat);
     *out = s;
     return ok();
   } catch (const std::bad_alloc&) {
@@ -636,3 +638,93 @@ pr_status pr_scene_destroy(pr_scene* s) {
 }
 
 }  // extern "C"
+
+extern "C" pr_status pr_scene_add_mesh(pr_scene* s, const float* vertices, uint32_t n_vertices,
+                                       const uint32_t* indices, uint32_t n_triangles,
+                                       const pr_instance* instances, uint32_t n_instances) {
+  try {
+    if (!s || !vertices || !indices || !instances) return set_error(PR_ERR_INVALID_ARG, "NULL argument");
+    if (n_vertices < 3 || n_triangles == 0 || n_instances == 0)
+      return set_error(PR_ERR_INVALID_ARG, "need >= 3 vertices, >= 1 triangle and >= 1 instance");
+    const uint64_t total = (uint64_t)s->host_insts.size() + (uint64_t)n_triangles * n_instances;
+    if (total > kMaxInstances)
+      return set_error(PR_ERR_INVALID_ARG, "scene would hold %llu items, at most %u",
+                       (unsigned long long)total, kMaxInstances);
+    if (!finite3(vertices, (int)std::min<uint64_t>(3ull * n_vertices, 0x7fffffff)))
+      return set_error(PR_ERR_INVALID_ARG, "non-finite mesh vertex");
+    for (uint64_t k = 0; k < 3ull * n_triangles; ++k)
+      if (indices[k] >= n_vertices) return set_error(PR_ERR_INVALID_ARG, "mesh index %u out of range", indices[k]);
+    for (uint32_t i = 0; i < n_instances; ++i) {
+      if (instances[i].material >= s->mats.size())
+        return set_error(PR_ERR_INVALID_ARG, "mesh instance %u: material index out of range", i);
+      if (!finite3(instances[i].xform, 12))
+        return set_error(PR_ERR_INVALID_ARG, "mesh instance %u: non-finite transform", i);
+      double A[9], Ai[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) A[3 * r + c] = instances[i].xform[4 * r + c];
+      if (!(std::fabs(inv3(A, Ai)) > 1e-12))
+        return set_error(PR_ERR_INVALID_ARG, "mesh instance %u: |det A| <= 1e-12", i);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (scene_busy(s)) return set_error(PR_ERR_BUSY, "renders of this scene are in flight");
+    std::vector<InstDev> add;
+    std::vector<float> add_shade, add_box;
+    add.reserve((size_t)n_triangles * n_instances);
+    for (uint32_t i = 0; i < n_instances; ++i) {
+      const float* X = instances[i].xform;
+      auto world = [&](uint32_t v, double out[3]) {
+        const float* p = vertices + 3 * (size_t)v;
+        for (int r = 0; r < 3; ++r)
+          out[r] = (double)X[4 * r] * p[0] + (double)X[4 * r + 1] * p[1] + (double)X[4 * r + 2] * p[2] + X[4 * r + 3];
+      };
+      for (uint32_t f = 0; f < n_triangles; ++f) {
+        double v0[3], v1[3], v2[3];
+        world(indices[3 * (size_t)f], v0);
+        world(indices[3 * (size_t)f + 1], v1);
+        world(indices[3 * (size_t)f + 2], v2);
+        double e1[3], e2[3];
+        for (int r = 0; r < 3; ++r) {
+          e1[r] = v1[r] - v0[r];
+          e2[r] = v2[r] - v0[r];
+        }
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        const double area2 = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const double scale = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]) *
+                             std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        if (!(area2 > 1e-9 * scale) || !(area2 > 0))
+          return set_error(PR_ERR_INVALID_ARG, "mesh instance %u, triangle %u: degenerate", i, f);
+        InstDev d;
+        std::memset(&d, 0, sizeof d);
+        for (int r = 0; r < 3; ++r) {
+          d.Ainv[r] = (float)v0[r];
+          d.Ainv[3 + r] = (float)e1[r];
+          d.Ainv[6 + r] = (float)e2[r];
+          d.b[r] = (float)(n[r] / area2);
+          d.lo[r] = (float)std::min({v0[r], v1[r], v2[r]});
+          d.hi[r] = (float)std::max({v0[r], v1[r], v2[r]});
+        }
+        d.sigma = 1.f;
+        d.type = kTriangle;
+        const uint32_t uid = (uint32_t)(s->host_insts.size() + add.size());
+        std::memcpy(&d.prm[7], &uid, 4);
+        add.push_back(d);
+        const pr_material& m = s->mats[instances[i].material];
+        add_shade.insert(add_shade.end(), {m.albedo[0], m.albedo[1], m.albedo[2], m.reflectivity});
+        add_box.insert(add_box.end(), {d.lo[0], d.lo[1], d.lo[2], d.hi[0], d.hi[1], d.hi[2]});
+      }
+    }
+    free_device(s);
+    s->built = false;
+    s->host_insts.insert(s->host_insts.end(), add.begin(), add.end());
+    s->host_shade.insert(s->host_shade.end(), add_shade.begin(), add_shade.end());
+    s->world_aabb.insert(s->world_aabb.end(), add_box.begin(), add_box.end());
+    s->consts.n_inst = (uint32_t)s->host_insts.size();
+    s->n_types_present |= 1u << kTriangle;
+    return ok();
+  } catch (const std::bad_alloc&) {
+    return set_error(PR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return set_error(PR_ERR_DEVICE, "unexpected exception");
+  }
+}

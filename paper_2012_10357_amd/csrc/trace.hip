@@ -123,6 +123,26 @@ __device__ __forceinline__ void tile_at(const ReqDev* R, uint32_t q, uint32_t& t
   tx = q % nx;
 }
 
+// Ray-triangle distance in world space (Moeller-Trumbore; double-sided,
+// closed barycentric bounds), +inf when the ray's line misses the triangle.
+// The record holds v0 in Ainv[0..2], e1 = v1 - v0 in Ainv[3..5] and
+// e2 = v2 - v0 in Ainv[6..8].
+__device__ __forceinline__ float triangle_hit(const InstDev& I, float ox, float oy, float oz, float dx,
+                                              float dy, float dz) {
+  const float e1x = I.Ainv[3], e1y = I.Ainv[4], e1z = I.Ainv[5];
+  const float e2x = I.Ainv[6], e2y = I.Ainv[7], e2z = I.Ainv[8];
+  const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+  const float det = e1x * px + e1y * py + e1z * pz;
+  const float inv = 1.0f / det;
+  const float sx = ox - I.Ainv[0], sy = oy - I.Ainv[1], sz = oz - I.Ainv[2];
+  const float u = (sx * px + sy * py + sz * pz) * inv;
+  const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+  const float v = (dx * qx + dy * qy + dz * qz) * inv;
+  const float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+  const bool in = det != 0.f && u >= 0.f && u <= 1.f && v >= 0.f && u + v <= 1.f;
+  return in ? t : __builtin_inff();
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(const ReqDev* __restrict__ reqs,
                                                        QueueDev* __restrict__ queue,
@@ -224,10 +244,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   const SceneConstsDev* sc = nullptr;
   uint32_t lim_nodes = 0, lim_insts = 0;   // indices below these are read from LDS
 
-  auto node_ptr = [&](uint32_t i) -> const NodeDev* {
+  auto node_ptr = [&](uint32_t i) __attribute__((always_inline)) -> const NodeDev* {
     return i < lim_nodes ? &lds_nodes[i] : &nodes[i];
   };
-  auto inst_ptr = [&](int i) -> const InstDev* {
+  auto inst_ptr = [&](int i) __attribute__((always_inline)) -> const InstDev* {
     return (uint32_t)i < lim_insts ? &lds_insts[i] : &insts[i];
   };
   uint32_t max_steps = 1;
@@ -239,7 +259,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   // the last stretch of the queue, about one chunk per wave of the grid
   const uint32_t tail_jobs = gridDim.x * (uint32_t)kWavesPerBlock * kChunk;
 
-  auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) {
+  auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) __attribute__((always_inline)) {
     ray = r;
     kind = k;
     tmin = t_lo;
@@ -255,7 +275,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (COUNT) atomicAdd(&cnt_lds[28 + (k == K_HSHADOW ? K_SHADOW : k)], 1ull);
   };
 
-  auto primary_ray = [&]() {
+  auto primary_ray = [&]() __attribute__((always_inline)) {
     const float ex = R->eye[0], ey = R->eye[1], ez = R->eye[2];
     float fx = R->target[0] - ex, fy = R->target[1] - ey, fz = R->target[2] - ez;
     float fl = 1.0f / __builtin_sqrtf(fx * fx + fy * fy + fz * fz);
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   // performed, then bumps the pixel's sample counter.  The sample that
   // completes the count takes the sums with atomic exchanges, which also
   // clear the accumulators for the next launch, and writes the mean.
-  auto finish_sample = [&](float cr, float cg, float cb) {
+  auto finish_sample = [&](float cr, float cg, float cb) __attribute__((always_inline)) {
     const size_t pix = (size_t)py * R->width + px;
     float* o = R->out_rgb + pix * 3;
     if (spp == 1) {
@@ -320,7 +340,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     mode = M_IDLE;
   };
 
-  auto bind_request = [&](uint32_t a) {
+  auto bind_request = [&](uint32_t a) __attribute__((always_inline)) {
     req_i = a;
     R = a < kLdsReqs ? &lds_reqs[a] : reqs + a;
     insts = R->insts;
@@ -339,7 +359,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     spp = R->spp;
   };
 
-  auto start_job = [&](uint32_t j) {
+  auto start_job = [&](uint32_t j) __attribute__((always_inline)) {
     // locate the request (few requests: linear; many: binary search)
     uint32_t a = 0, b = n_req;
     while (b - a > 1) {
@@ -368,9 +388,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     primary_ray();
   };
 
-  // set up a candidate: local ray, clip, march state; returns true if marching
-  auto try_candidate = [&](int slot) -> bool {
+  // set up a candidate: local ray, clip, march state; returns true if the lane
+  // leaves traversal (marching it, or a shadow ray found an occluder).
+  // Triangles are intersected in closed form here (Moeller-Trumbore, world
+  // space, double-sided) and never marched.
+  auto try_candidate = [&](int slot) __attribute__((always_inline)) -> bool {
     const InstDev& I = *inst_ptr(slot);
+    if (I.type == kTriangle) {
+      // the hit distance becomes a one-step "march" whose estimate is 0, so
+      // the burst records it under the same closest-/any-hit rules
+      if (COUNT) ++c_clips;
+      const float th = triangle_hit(I, ray.ox, ray.oy, ray.oz, ray.dx, ray.dy, ray.dz);
+      if (!(th >= tmin && th <= limit)) return false;
+      cur_slot = slot;
+      cur_type = kTriangle;
+      sigma = 1.f;
+      t = th;
+      t1 = th;
+      steps = 0;
+      cut_line[tid] = make_float2(-__builtin_inff(), 0.f);
+      mode = M_MARCH;
+      return true;
+    }
     float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
     float ol[3], dl[3];
     ol[0] = I.Ainv[0] * d0 + I.Ainv[1] * d1 + I.Ainv[2] * d2;
@@ -406,11 +445,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   // traversal until a candidate is being marched or the ray is finished.
   // Stack entries (16 bit): an interior node index, or 0x8000 | node << 1 |
   // child for a leaf child whose candidates are deferred (the far child).
-  auto traverse = [&]() {
+  auto traverse = [&]() __attribute__((always_inline)) {
     const float ix = 1.0f / (ray.dx != 0.f ? ray.dx : copysignf(1e-30f, ray.dx));
     const float iy = 1.0f / (ray.dy != 0.f ? ray.dy : copysignf(1e-30f, ray.dy));
     const float iz = 1.0f / (ray.dz != 0.f ? ray.dz : copysignf(1e-30f, ray.dz));
-    auto box_entry = [&](const float* lo, const float* hi) -> float {
+    auto box_entry = [&](const float* lo, const float* hi) __attribute__((always_inline)) -> float {
       float tx0 = (lo[0] - ray.ox) * ix, tx1 = (hi[0] - ray.ox) * ix;
       float ty0 = (lo[1] - ray.oy) * iy, ty1 = (hi[1] - ray.oy) * iy;
       float tz0 = (lo[2] - ray.oz) * iz, tz1 = (hi[2] - ray.oz) * iz;
@@ -459,9 +498,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
   };
 
-  auto start_normal = [&](int slot, float th) {
+  auto start_normal = [&](int slot, float th) __attribute__((always_inline)) {
     const InstDev* ip = inst_ptr(slot);
     const InstDev& I = *ip;
+    if (I.type == kTriangle) {
+      // face normal from the record, no estimator taps
+      cur_slot = slot;
+      t = th;
+      mode = M_NORMAL_READY;
+      return;
+    }
     float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
     float ol0 = I.Ainv[0] * d0 + I.Ainv[1] * d1 + I.Ainv[2] * d2;
     float ol1 = I.Ainv[3] * d0 + I.Ainv[4] * d1 + I.Ainv[5] * d2;
@@ -482,7 +528,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
   // mirror bounce from the primary hit: r = d - 2 (d.n) n, origin offset
   // along the normal
-  auto start_bounce = [&]() {
+  auto start_bounce = [&]() __attribute__((always_inline)) {
     float dn = bounce_ray.dx * hnx + bounce_ray.dy * hny + bounce_ray.dz * hnz;
     float rx = bounce_ray.dx - 2.f * dn * hnx;
     float ry = bounce_ray.dy - 2.f * dn * hny;
@@ -494,7 +540,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
   // run the handed-off shadow ray of lane `owner` (another lane's, or this
   // lane's own when nobody took it)
-  auto run_handoff = [&](int owner) {
+  auto run_handoff = [&](int owner) __attribute__((always_inline)) {
     help_owner = owner;
     if (owner != lane) {
       bind_request(tk_ref[wv][owner] >> 14);
@@ -510,17 +556,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   };
 
   // normal finished: shade prep, spawn the shadow ray (or skip it)
-  auto after_normal = [&]() {
+  auto after_normal = [&]() __attribute__((always_inline)) {
     const InstDev& I = *inst_ptr(cur_slot);
-    float nx = I.Ainv[0] * gx + I.Ainv[3] * gy + I.Ainv[6] * gz;   // A^-T g
-    float ny = I.Ainv[1] * gx + I.Ainv[4] * gy + I.Ainv[7] * gz;
-    float nz = I.Ainv[2] * gx + I.Ainv[5] * gy + I.Ainv[8] * gz;
-    float ln = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
-    if (ln > 0.f) {
-      float il = 1.0f / ln;
-      nx *= il; ny *= il; nz *= il;
+    float nx, ny, nz;
+    if (I.type == kTriangle) {
+      // double-sided: the face normal turned toward the incoming ray
+      const float fx = I.b[0], fy = I.b[1], fz = I.b[2];
+      const float side = (fx * ray.dx + fy * ray.dy + fz * ray.dz) > 0.f ? -1.f : 1.f;
+      nx = side * fx;
+      ny = side * fy;
+      nz = side * fz;
     } else {
-      nx = -ray.dx; ny = -ray.dy; nz = -ray.dz;
+      nx = I.Ainv[0] * gx + I.Ainv[3] * gy + I.Ainv[6] * gz;   // A^-T g
+      ny = I.Ainv[1] * gx + I.Ainv[4] * gy + I.Ainv[7] * gz;
+      nz = I.Ainv[2] * gx + I.Ainv[5] * gy + I.Ainv[8] * gz;
+      float ln = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
+      if (ln > 0.f) {
+        float il = 1.0f / ln;
+        nx *= il; ny *= il; nz *= il;
+      } else {
+        nx = -ray.dx; ny = -ray.dy; nz = -ray.dz;
+      }
     }
     float hx = ray.ox + t * ray.dx, hy = ray.oy + t * ray.dy, hz = ray.oz + t * ray.dz;
     float lx = sc->light[0] - hx, ly = sc->light[1] - hy, lz = sc->light[2] - hz;
@@ -561,7 +617,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
   };
 
-  auto lambert = [&](float V, float& cr, float& cg, float& cb) {
+  auto lambert = [&](float V, float& cr, float& cg, float& cb) __attribute__((always_inline)) {
     const float amb = sc->ambient;
     cr = sh_ar * (amb + V * sh_lam * sc->light_rgb[0]);
     cg = sh_ag * (amb + V * sh_lam * sc->light_rgb[1]);
@@ -571,7 +627,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   // The owner of a handed-off shadow ray, its bounce colour kept in p_c*:
   // combine once the primary colour is published, run the shadow ray itself
   // if no lane took it, or wait for the lane that did.
-  auto collect = [&]() {
+  auto collect = [&]() __attribute__((always_inline)) {
     const uint32_t st = tk_state[wv][lane];
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (st == T_DONE) {
@@ -590,7 +646,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   };
 
   // the mirror bounce's colour is known: blend with the primary colour
-  auto end_bounce = [&](float br, float bg, float bb) {
+  auto end_bounce = [&](float br, float bg, float bb) __attribute__((always_inline)) {
     if (donated) {
       p_cr = br;
       p_cg = bg;
@@ -604,7 +660,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   };
 
   // a ray has finished traversal: move the pixel's pipeline forward
-  auto ray_done = [&]() {
+  auto ray_done = [&]() __attribute__((always_inline)) {
     switch (kind) {
       case K_PRIMARY: {
         if (s == 0) {
@@ -740,7 +796,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 
     // control: advance every lane to its next estimator evaluation
-    auto control = [&]() {
+    auto control = [&]() __attribute__((always_inline)) {
       while (has_job && mode != M_MARCH && mode != M_NORMAL && mode != M_WAIT) {
         if (mode == M_TRAVERSE) {
           traverse();
@@ -836,11 +892,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float qy = lo_[1] + t * ld_[1];
         const float qz = lo_[2] + t * ld_[2];
         int iters;
-        float de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        float de = cur_type == kTriangle ? 0.f : de_eval(cur_type, qx, qy, qz, prm, &iters);
         const float2 cl = cut_line[tid];
         if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
         ++job_evals;
-        if (COUNT) {
+        if (COUNT && cur_type < kTriangle) {
           atomicAdd(&cnt_lds[cur_type], 1ull);
           atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
         }

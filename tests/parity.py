@@ -2,9 +2,10 @@
 
 Pixels are excluded where the oracle saw any traced ray graze a surface
 within 1e-3 without stopping (E1), exhaust its step budget (E2), stop with
-a value in [0.98 eps, eps) (E3), or hit where the normal is ill-conditioned
-at the scale of float32 rounding of the hit point (E4): there float32 and
-float64 may legitimately take different branches.  On the remaining pixels:
+a value in [0.98 eps, eps) (E3), hit where the normal is ill-conditioned
+at the scale of float32 rounding of the hit point (E4), or meet a triangle
+within 1e-5 of an edge, at a grazing angle, or tied with a procedural hit
+(E5): there float32 and float64 may legitimately take different branches.  On the remaining pixels:
   * hit mask agreement >= 99.9 %,
   * hit distance |t_g - t_o| <= 1e-4 t_o on >= 99.9 % of pixels hit by both,
   * radiance max_c |L_g - L_o| <= 1e-3 on >= 99.9 % of pixels whose masks agree.
@@ -44,6 +45,7 @@ def compare(g_rgb, g_t, g_inst, orc, label=""):
         excl_e1=float(((orc["excl"] & 1) != 0).mean()), excl_e2=float(((orc["excl"] & 2) != 0).mean()),
         excl_e3=float(((orc["excl"] & 4) != 0).mean()),
         excl_e4=float(((orc["excl"] & 8) != 0).mean()),
+        excl_e5=float(((orc["excl"] & 16) != 0).mean()),
         hit_frac=float(mo.mean()), mask=frac_mask, mask_all=frac_mask_all, inst=inst_agree,
         t_frac=frac_t, t_max=float(t_err[both].max()) if both.any() else 0.0,
         rgb_frac=frac_rgb, rgb_max=float(rgb_err[sel].max()) if sel.any() else 0.0,
@@ -55,7 +57,7 @@ def compare(g_rgb, g_t, g_inst, orc, label=""):
 
 
 def fmt(rep):
-    return ("{label}: px={pixels} excl={excluded:.4f} (E1 {excl_e1:.4f} E2 {excl_e2:.4f} E3 {excl_e3:.4f} E4 {excl_e4:.4f}) "
+    return ("{label}: px={pixels} excl={excluded:.4f} (E1 {excl_e1:.4f} E2 {excl_e2:.4f} E3 {excl_e3:.4f} E4 {excl_e4:.4f} E5 {excl_e5:.4f}) "
             "hit={hit_frac:.3f} mask={mask:.5f} mask_all={mask_all:.5f} inst={inst:.5f} "
             "t_frac={t_frac:.5f} t_max={t_max:.2e} rgb_frac={rgb_frac:.5f} rgb_max={rgb_max:.2e} "
             "rgb_p999={rgb_p999:.2e} rgb_frac_all={rgb_frac_all:.5f} pass={pass}").format(**rep)

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == 2
+    assert P.abi_version() == 3
     assert P.device_count() >= 0
 
 
@@ -163,4 +163,39 @@ def test_bvh_well_formed_and_culls_like_brute_force(P, max_leaf):
                 stack += [first[i], first[i] + 1]
         brute = {k for k in range(n) if box_hit(o[r], d[r], wlo[k], whi[k])}
         assert brute <= found
+    sc.close()
+
+
+def test_mesh_validation_and_bvh_items(P):
+    """pr_scene_add_mesh validates before touching anything; every (placement,
+    triangle) pair becomes one BVH leaf item after the procedural instances."""
+    desc = W.f2_sample_scene()
+    sc = P.Scene(desc, build=False)
+    sc.build(P.BvhOpts(32, 1, 1.0, 4.0, P.PR_BVH_HOST_ONLY))
+    order = sc.bvh()[4]
+    assert sorted(order.tolist()) == list(range(desc.n_inst + 2))
+    quad_v, quad_f = np.array(W.QUAD_VERTICES, np.float32), np.array(W.QUAD_INDICES, np.uint32)
+    xf = [W.xform(np.eye(3), 1.0, (0, 0, 0))]
+    with pytest.raises(P.ProcrayError, match="index"):
+        sc.add_mesh(quad_v, np.array([[0, 1, 7]], np.uint32), [0], xf)
+    bad_v = quad_v.copy(); bad_v[1, 1] = np.inf
+    with pytest.raises(P.ProcrayError, match="non-finite"):
+        sc.add_mesh(bad_v, quad_f, [0], xf)
+    with pytest.raises(P.ProcrayError, match="degenerate"):
+        sc.add_mesh(np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32), np.array([[0, 1, 2]], np.uint32),
+                    [0], xf)
+    with pytest.raises(P.ProcrayError, match="material"):
+        sc.add_mesh(quad_v, quad_f, [99], xf)
+    with pytest.raises(P.ProcrayError, match="det"):
+        sc.add_mesh(quad_v, quad_f, [0], [np.zeros(12, np.float32)])
+    with pytest.raises(P.ProcrayError, match="at most"):
+        sc.add_mesh(quad_v, quad_f, [0] * 8200, xf * 8200)
+    # the failed calls changed nothing: the build still holds 4 + 2 items;
+    # a valid addition clears the build
+    sc.add_mesh(quad_v, quad_f, [0, 1], xf * 2)
+    with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
+        sc.bvh()
+    sc.build(P.BvhOpts(32, 1, 1.0, 4.0, P.PR_BVH_HOST_ONLY))
+    order = sc.bvh()[4]
+    assert sorted(order.tolist()) == list(range(desc.n_inst + 2 + 4))
     sc.close()

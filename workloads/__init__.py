@@ -59,6 +59,9 @@ class Scene:
     ambient: float
     background: np.ndarray     # (3,) float32
     geom_cut: Optional[np.ndarray] = None   # (G, 4) float32: kept half-space n.p <= d; n = 0: none
+    # triangle meshes: dicts of vertices (V, 3) f32, indices (F, 3) u32 and one
+    # placement per entry of inst_mat (K,) u32 / inst_xform (K, 12) f32
+    meshes: Optional[list] = None
 
     @property
     def n_inst(self) -> int:
@@ -200,6 +203,7 @@ def geom_mandelbulb(power=8, n_iter=10, bailout=2.0, half=1.2):
 class _SceneBuilder:
     def __init__(self):
         self.gt, self.ga, self.gp, self.gc = [], [], [], []
+        self.meshes = []
         self.ig, self.im, self.ix = [], [], []
         self.alb, self.refl = [], []
 
@@ -215,6 +219,14 @@ class _SceneBuilder:
     def instance(self, geom: int, mat: int, xf: np.ndarray):
         self.ig.append(geom); self.im.append(mat); self.ix.append(xf)
 
+    def mesh(self, vertices, indices, placements):
+        """placements: sequence of (material, 3x4 row-major local-to-world)."""
+        self.meshes.append(dict(
+            vertices=_f32(vertices).reshape(-1, 3),
+            indices=np.asarray(indices, np.uint32).reshape(-1, 3),
+            inst_mat=np.asarray([m for m, _ in placements], np.uint32),
+            inst_xform=_f32([x for _, x in placements]).reshape(-1, 12)))
+
     def build(self, light_pos, light_rgb=(1, 1, 1), ambient=0.1, background=(0, 0, 0)) -> Scene:
         return Scene(
             geom_type=np.asarray(self.gt, np.uint32),
@@ -228,6 +240,7 @@ class _SceneBuilder:
             light_pos=_f32(light_pos), light_rgb=_f32(light_rgb),
             ambient=float(np.float32(ambient)), background=_f32(background),
             geom_cut=_f32(self.gc).reshape(-1, 4),
+            meshes=self.meshes or None,
         )
 
 
@@ -450,6 +463,38 @@ def f1_mandelbulb_anim(width=256, height=256, steps=None) -> Workload:
                                tmax=100.0, shadows=1, bounces=0))
             for n in steps]
     return Workload("f1_mandelbulb_animation", [f1_mandelbulb_anim_scene()], reqs)
+
+
+# The paper's sample scene (Fig. 4): a triangle plane mesh under the two
+# pac-men, the Julia set and the Mandelbulb of the teaser.
+QUAD_VERTICES = [(-1.0, 0.0, -1.0), (1.0, 0.0, -1.0), (1.0, 0.0, 1.0), (-1.0, 0.0, 1.0)]
+QUAD_INDICES = [(0, 1, 2), (0, 2, 3)]
+
+
+def f2_sample_scene() -> Scene:
+    """The teaser scene plus a 16 x 16 grey plane of two triangles at y = -1.1."""
+    rng = np.random.default_rng(config_seed(2))
+    b = _SceneBuilder()
+    m_pac = b.material((1.0, 0.85, 0.1), 0.3)
+    m_jul = b.material((0.3, 0.6, 1.0), 0.3)
+    m_man = b.material((0.9, 0.4, 0.3), 0.3)
+    m_pln = b.material((0.75, 0.75, 0.75), 0.0)
+    g_pac = b.geometry(geom_pacman(0.8, 60.0))
+    c = rng.uniform(-0.8, 0.8, 4)
+    g_jul = b.geometry(geom_julia(c, 12, 4.0))
+    g_man = b.geometry(geom_mandelbulb(8, 10, 2.0))
+    yaw0, yaw1 = rng.uniform(0.0, 2.0 * math.pi, 2)
+    b.instance(g_pac, m_pac, xform(_rot_y(yaw0), 1.0, (-2.2, 0.0, 0.5)))
+    b.instance(g_pac, m_pac, xform(_rot_y(yaw1), 1.0, (2.2, 0.0, 0.5)))
+    b.instance(g_jul, m_jul, xform(np.eye(3), 0.6, (-0.8, 0.1, -0.6)))
+    b.instance(g_man, m_man, xform(_rot_x(-math.pi / 2), 0.9, (0.9, 0.1, -0.9)))
+    b.mesh(QUAD_VERTICES, QUAD_INDICES, [(m_pln, xform(np.eye(3), 8.0, (0.0, -1.1, 0.0)))])
+    return b.build(light_pos=(2, 4, -3))
+
+
+def f2_sample(width=1920, height=1080) -> Workload:
+    return Workload("f2_sample_scene_plane", [f2_sample_scene()],
+                    [Request(0, c2_camera(), c2_opts(width, height))])
 
 
 def pixel_sample(width: int, height: int, n: int, seed: int) -> np.ndarray:
