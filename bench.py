@@ -177,6 +177,63 @@ def bench_batched(P, W, torch, dev):
             "tuned": {"tile": [best.tile_w, best.tile_h], "step_budget": best.step_budget}}
 
 
+def _frame_rate(P, torch, dev, sc, cam, opts, reps=5):
+    """Rays, algorithmic flops and mean kernel time of one frame."""
+    rgb = torch.empty((opts.height, opts.width, 3), dtype=torch.float32, device=dev)
+    counts = P.render_counts(sc, cam, opts, rgb)
+    rays = int(sum(ray_breakdown(counts).values()))
+    flops = algorithmic_flops(counts)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        P.render(sc, cam, opts, rgb, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            P.render(sc, cam, opts, rgb, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"ms": round(ms, 3), "mrays_s": round(rays / ms / 1e3, 1),
+            "tflops": round(float(flops) / ms / 1e9, 3), "rays": rays}
+
+
+def bench_next(P, W, torch, dev):
+    """The next-step features at 1080p: the sample scene with its triangle
+    plane, the Julia set cut by each plane, and the twelve-frame step-budget
+    animation of the Mandelbulb rendered as one batched launch."""
+    out = {}
+    wl = W.f2_sample()
+    sc = P.Scene(wl.scenes[0])
+    out["sample_scene_plane_1080p"] = _frame_rate(P, torch, dev, sc, wl.requests[0].camera, wl.requests[0].opts)
+    sc.close()
+    wl = W.f1_julia_cut(1920, 1080)
+    for k, r in enumerate(wl.requests):
+        sc = P.Scene(wl.scenes[r.scene_index])
+        out[f"julia_cut{k}_1080p"] = _frame_rate(P, torch, dev, sc, r.camera, r.opts)
+        sc.close()
+    wl = W.f1_mandelbulb_anim(1024, 1024)
+    sc = P.Scene(wl.scenes[0])
+    outs = [torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev) for r in wl.requests]
+    rays = 0
+    for r, o in zip(wl.requests, outs):
+        rays += int(sum(ray_breakdown(P.render_counts(sc, r.camera, r.opts, o)).values()))
+    reqs = P.make_requests([(sc, r.camera, r.opts, o, None, None, i) for i, (r, o) in enumerate(zip(wl.requests, outs))])
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        P.render_batch(reqs, use_graph=True, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            P.render_batch(reqs, use_graph=True, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 3
+    out["mandelbulb_animation_12x1024sq_batched"] = {"ms": round(ms, 3), "frames_s": round(12e3 / ms, 1),
+                                                     "mrays_s": round(rays / ms / 1e3, 1), "rays": rays}
+    sc.close()
+    return out
+
+
 def bench_served(P, W, torch, dev, seconds):
     """Open-loop Poisson trace at 200 req/s over 8 resident scenes: the
     continuous-batching server vs FIFO per-request pr_render launches."""
@@ -261,6 +318,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-next", action="store_true", help="skip the cut / mesh / animation lines")
     ap.add_argument("--served-seconds", type=float, default=3.0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--budget", type=int, default=0)
@@ -345,6 +403,9 @@ def main():
     if not args.no_served:
         out["served"] = bench_served(P, W, torch, dev, args.served_seconds)
         print(f"# served: {out['served']}", file=sys.stderr, flush=True)
+    if not args.no_next:
+        out["next"] = bench_next(P, W, torch, dev)
+        print(f"# next: {out['next']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
