@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 3
+#define PR_ABI_VERSION 4
 
 typedef enum {
   PR_OK = 0,
@@ -188,6 +188,33 @@ pr_status pr_scene_device_bytes(const pr_scene* scene, uint64_t* bytes);
 
 /* Frees host and device memory.  PR_ERR_BUSY while renders are in flight. */
 pr_status pr_scene_destroy(pr_scene* scene);
+
+/* ---------------------------------------------------------- user estimators */
+
+/* Programmable primitives (the flexibility the paper's hit groups and shader
+ * tables give, Sec. 2.2.3 and Sec. 3, Eq. 1): a distance estimator supplied
+ * as HIP C++ source and compiled into the trace kernel at run time.
+ *  name   identifier [A-Za-z_][A-Za-z0-9_]*, at most 48 characters
+ *  body   the body of
+ *           template <typename R> R est(R x, R y, R z, const float* p)
+ *         returning a lower bound on the distance from the local point
+ *         (x, y, z) to the surface (negative inside), with p the geometry's
+ *         params[0..6] (params[7] is not passed); R is float in the march and
+ *         double in the normal taps.
+ * On success *type_out receives the new primitive type (PR_USER_TYPE_BASE +
+ * k, at most PR_MAX_USER_TYPES per process) for pr_geometry.type.  Launches
+ * touching a scene with such a type use a code object built on first use by
+ * running hipcc (PR_HIPCC, else /opt/rocm/bin/hipcc) with the library's own
+ * flags into a cache directory (PR_USER_CACHE, else $TMPDIR or /tmp); a
+ * compile error returns PR_ERR_INVALID_ARG from that render with the
+ * compiler's message in pr_last_error().  Registration copies the strings. */
+#define PR_USER_TYPE_BASE 8u
+#define PR_MAX_USER_TYPES 16u
+pr_status pr_register_estimator(const char* name, const char* body, uint32_t* type_out);
+/* Compiles the registered estimators now (no device needed), so that source
+ * errors surface here rather than at the first render: PR_ERR_INVALID_ARG
+ * with the compiler's message.  PR_OK when nothing is registered. */
+pr_status pr_build_estimators(void);
 
 /* ---------------------------------------------------------------- rendering */
 

@@ -177,6 +177,15 @@ def de_mandelbulb(p, power, n_iter, bailout, algebraic=False):
     return np.where(r < TINY, 0.0, de), iters
 
 
+# User estimators (the programmable primitives of the library): type id ->
+# function (points (m, 3), params (m, 8)) -> distance bounds (m,), float64.
+USER = {}
+
+
+def register_estimator(gtype: int, fn) -> None:
+    USER[int(gtype)] = fn
+
+
 def de_eval(gtype: int, p: np.ndarray, prm: np.ndarray):
     """Evaluate the estimator of one primitive type at points p (m, 3).
 
@@ -187,6 +196,8 @@ def de_eval(gtype: int, p: np.ndarray, prm: np.ndarray):
     if prm.ndim == 1:
         prm = np.broadcast_to(prm, (p.shape[0], 8))
     zero = np.zeros(p.shape[0], np.int64)
+    if gtype in USER:
+        return np.asarray(USER[gtype](p, prm), np.float64), zero
     if gtype == SPHERE:
         return de_sphere(p, prm[:, 0]), zero
     if gtype == BOX:

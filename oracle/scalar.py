@@ -46,6 +46,14 @@ def _box(p, c, h):
 
 
 def _de(gt, p, prm):
+    from .de import USER
+    if gt in USER:
+        import numpy as np
+        return float(USER[gt](np.array([p], np.float64), np.array([prm], np.float64))[0]), 0
+    return _de_builtin(gt, p, prm)
+
+
+def _de_builtin(gt, p, prm):
     """Returns (DE, iterations)."""
     if gt == 0:
         return _len(p) - prm[0], 0

@@ -547,8 +547,9 @@ def _count_canonical(prep, R, K, T0, res, hist, m, mode, counts):
             nn = h["n"][j]
             Tj = h["T"][j, :nn]
             use = Tj <= best[ray]
-            counts.evals[gt] += int(use.sum())
-            counts.iters[gt] += int(h["IT"][j, :nn][use].sum())
+            if gt < counts.evals.size:   # user estimators are not counted
+                counts.evals[gt] += int(use.sum())
+                counts.iters[gt] += int(h["IT"][j, :nn][use].sum())
             if h["out"][j] == HIT:
                 if mode == "any":
                     done[ray] = True
@@ -577,8 +578,9 @@ def normals(prep, inst, ol, dl, t, d_world, h_fd, counts=None):
             vm = apply_cut(vm, p_l[sel] - dp, prep.cut[inst[sel]])
             g[sel, ax] = vp - vm
             if counts is not None:
-                counts.normal_evals[gt] += 2 * sel.size
-                counts.normal_iters[gt] += int(itp.sum() + itm.sum())
+                if gt < counts.normal_evals.size:
+                    counts.normal_evals[gt] += 2 * sel.size
+                    counts.normal_iters[gt] += int(itp.sum() + itm.sum())
     nw = np.einsum("kji,kj->ki", prep.Ainv[inst], g)       # A^-T g
     ln = np.linalg.norm(nw, axis=1)
     zero = ~(ln > 0)

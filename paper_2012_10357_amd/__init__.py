@@ -31,7 +31,7 @@ EXPORTS = [
     "pr_scene_destroy", "pr_render", "pr_render_counts", "pr_render_batch", "pr_autotune",
     "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
-    "pr_abi_version", "pr_device_count", "pr_launch_shape",
+    "pr_abi_version", "pr_device_count", "pr_launch_shape", "pr_register_estimator", "pr_build_estimators",
 ]
 
 
@@ -154,6 +154,8 @@ def lib():
         "pr_server_stats_get": [P, P],
         "pr_server_destroy": [P],
         "pr_launch_shape": [C.POINTER(U32), C.POINTER(U32)],
+        "pr_register_estimator": [C.c_char_p, C.c_char_p, C.POINTER(U32)],
+        "pr_build_estimators": [],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -384,6 +386,18 @@ class Server:
 
 def device_count() -> int:
     return int(lib().pr_device_count())
+
+
+def register_estimator(name: str, body: str) -> int:
+    """pr_register_estimator: returns the new primitive type for pr_geometry."""
+    t = C.c_uint32(0)
+    _check(lib().pr_register_estimator(name.encode(), body.encode(), C.byref(t)))
+    return int(t.value)
+
+
+def build_estimators():
+    """pr_build_estimators: compile the registered estimators now."""
+    _check(lib().pr_build_estimators())
 
 
 def launch_shape():

@@ -136,6 +136,19 @@ struct LaunchCfg {
 
 // Kernel launch entry points (defined in trace.hip).
 namespace pr {
+// Run-time build with user estimators (user_de.cpp).
+bool user_type_registered(uint32_t type);
+struct UserKernels {
+  void* plain = nullptr;      // hipFunction_t of pr_trace_user
+  void* counting = nullptr;   // hipFunction_t of pr_trace_user_count
+  int blocks_per_cu = 1;
+};
+// Loads (building on first use) the code object for the current registry on
+// the current device.  Sets the error message and returns non-OK on failure.
+pr_status user_kernels(UserKernels* out);
+int launch_trace_user(const UserKernels& k, const ReqDev* reqs_dev, QueueDev* queue_dev, const LaunchCfg& cfg,
+                      unsigned long long* counts_dev, void* stream);
+
 int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_jobs, uint32_t n_req,
                  const LaunchCfg& cfg, unsigned long long* counts_dev, void* stream);
 int device_cu_count();

@@ -295,12 +295,12 @@ void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_rende
 
 int g_blocks_per_cu = 0;
 
-int grid_for(uint32_t total_jobs) {
+int grid_for(uint32_t total_jobs, int blocks_per_cu = 0) {
   // persistent grid: as many workgroups as can be resident at once
   if (g_blocks_per_cu == 0) g_blocks_per_cu = occupancy_blocks_per_cu();
   int cus = device_cu_count();
   if (cus <= 0) cus = 256;
-  long want = (long)cus * g_blocks_per_cu;
+  long want = (long)cus * (blocks_per_cu > 0 ? blocks_per_cu : g_blocks_per_cu);
   long need = ((long)total_jobs + kBlock - 1) / kBlock;
   return (int)std::max(1L, std::min(want, need));
 }
@@ -378,10 +378,25 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   std::memcpy(c->host, &q, sizeof q);
   std::memcpy((char*)c->host + sizeof(QueueDev), table.data(), table.size() * sizeof(ReqDev));
   const size_t bytes = sizeof(QueueDev) + reqs.size() * sizeof(ReqDev);
-  LaunchCfg cfg{step_budget, grid_for(total_jobs)};
+  // scenes with user estimators run the kernel built with them
+  bool user = false;
+  for (pr_scene* s : scenes) user = user || (s->n_types_present >> PR_USER_TYPE_BASE) != 0;
+  UserKernels uk;
+  if (user) {
+    pr_status st = user_kernels(&uk);
+    if (st != PR_OK) {
+      release_ctx(c);
+      return st;
+    }
+  }
+  auto launch = [&](unsigned long long* counts, hipStream_t s, const LaunchCfg& cf) -> int {
+    const ReqDev* r0 = (const ReqDev*)((char*)c->dev + sizeof(QueueDev));
+    QueueDev* q0 = (QueueDev*)c->dev;
+    return user ? launch_trace_user(uk, r0, q0, cf, counts, s)
+                : launch_trace(r0, q0, total_jobs, (uint32_t)reqs.size(), cf, counts, s);
+  };
+  LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0)};
   hipError_t e;
-  const ReqDev* rd = (const ReqDev*)((char*)c->dev + sizeof(QueueDev));
-  QueueDev* qd = (QueueDev*)c->dev;
   bool graphed = false;
   if (use_graph && stream != nullptr && counts_dev == nullptr) {
     if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
@@ -394,7 +409,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
       e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         hipMemcpyAsync(c->dev, c->host, bytes, hipMemcpyHostToDevice, stream);
-        launch_trace(rd, qd, total_jobs, (uint32_t)reqs.size(), cfg, nullptr, stream);
+        launch(nullptr, stream, cfg);
         e = hipStreamEndCapture(stream, &g);
       }
       if (e == hipSuccess && g) {
@@ -426,7 +441,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
       release_ctx(c);
       return hip_fail(e, "hipMemcpyAsync(request table)");
     }
-    if (launch_trace(rd, qd, total_jobs, (uint32_t)reqs.size(), cfg, counts_dev, stream) != 0) {
+    if (launch(counts_dev, stream, cfg) != 0) {
       release_ctx(c);
       return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     }

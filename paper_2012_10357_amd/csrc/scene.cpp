@@ -175,6 +175,11 @@ pr_status pack_params(const pr_geometry& g, float out[8]) {
       break;
     }
     default:
+      if (user_type_registered(g.type)) {
+        // user estimator: parameters are passed through as given
+        for (int i = 0; i < 7; ++i) out[i] = p[i];
+        break;
+      }
       return set_error(PR_ERR_INVALID_ARG, "unknown primitive type %u", g.type);
   }
   return PR_OK;

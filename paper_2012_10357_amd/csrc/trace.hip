@@ -143,11 +143,10 @@ __device__ __forceinline__ float triangle_hit(const InstDev& I, float ox, float 
   return in ? t : __builtin_inff();
 }
 
+// The whole path for one workgroup; the kernels below wrap it.
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(const ReqDev* __restrict__ reqs,
-                                                       QueueDev* __restrict__ queue,
-                                                       int step_budget,
-                                                       unsigned long long* __restrict__ counts) {
+__device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue,
+                                           int step_budget, unsigned long long* __restrict__ counts) {
   __shared__ uint16_t stack_mem[kStackDepth][kBlock];
   __shared__ unsigned long long cnt_lds[COUNT ? kNumCounts : 1];
   __shared__ NodeDev lds_nodes[kLdsNodes];
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     src = (const uint4*)reqs;
     dst = (uint4*)lds_reqs;
     for (uint32_t i = tid; i < nr * (sizeof(ReqDev) / 16); i += kBlock) dst[i] = src[i];
-    if (COUNT)
+    if constexpr (COUNT)
       for (int i = tid; i < kNumCounts; i += kBlock) cnt_lds[i] = 0;
     __syncthreads();
   }
@@ -272,7 +271,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     leaf_i = 0;
     stack_mem[sp++][tid] = 0;
     mode = M_TRAVERSE;
-    if (COUNT) atomicAdd(&cnt_lds[28 + (k == K_HSHADOW ? K_SHADOW : k)], 1ull);
+    if constexpr (COUNT) atomicAdd(&cnt_lds[28 + (k == K_HSHADOW ? K_SHADOW : k)], 1ull);
   };
 
   auto primary_ray = [&]() __attribute__((always_inline)) {
@@ -613,7 +612,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       occluded = false;
       kind = (kind == K_PRIMARY) ? K_SHADOW : K_BSHADOW;
       mode = M_RAYDONE;
-      if (COUNT) { /* no ray launched */ }
     }
   };
 
@@ -849,7 +847,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             if (v == v) v = v > g ? v : g;
           }
           nrm_res[wv][tap][owner] = (float)v;
-          if (COUNT) {
+          if constexpr (COUNT) if (ty < PR_NUM_TYPES) {
             atomicAdd(&cnt_lds[14 + ty], 1ull);
             atomicAdd(&cnt_lds[21 + ty], (unsigned long long)iters);
           }
@@ -896,7 +894,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float2 cl = cut_line[tid];
         if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
         ++job_evals;
-        if (COUNT && cur_type < kTriangle) {
+        if constexpr (COUNT) if (cur_type < PR_NUM_TYPES) {
           atomicAdd(&cnt_lds[cur_type], 1ull);
           atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
         }
@@ -929,7 +927,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
   }
 
-  if (COUNT) {
+  if constexpr (COUNT) {
     atomicAdd(&cnt_lds[32], c_nodes);
     atomicAdd(&cnt_lds[33], c_clips);
     __syncthreads();
@@ -938,6 +936,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 }  // namespace
+
+#ifndef PR_USER_ESTIMATORS
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(
+    const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue, int step_budget,
+    unsigned long long* __restrict__ counts) {
+  trace_body<COUNT>(reqs, queue, step_budget, counts);
+}
 
 int device_cu_count() {
   int dev = 0, n = 0;
@@ -968,4 +975,21 @@ int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_job
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+#endif  // !PR_USER_ESTIMATORS
+
 }  // namespace pr
+
+#ifdef PR_USER_ESTIMATORS
+// Entry points of the run-time build that includes user estimators; looked
+// up by name in the loaded code object.
+extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user(
+    const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
+    unsigned long long* __restrict__ counts) {
+  pr::trace_body<false>(reqs, queue, step_budget, counts);
+}
+extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user_count(
+    const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
+    unsigned long long* __restrict__ counts) {
+  pr::trace_body<true>(reqs, queue, step_budget, counts);
+}
+#endif

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == 3
+    assert P.abi_version() == 4
     assert P.device_count() >= 0
 
 
@@ -199,3 +199,49 @@ def test_mesh_validation_and_bvh_items(P):
     order = sc.bvh()[4]
     assert sorted(order.tolist()) == list(range(desc.n_inst + 2 + 4))
     sc.close()
+
+
+def test_user_estimator_registration_and_build(P):
+    """Registering validates the name and body and hands out types from
+    PR_USER_TYPE_BASE; scenes accept registered types only; the estimators
+    compile with the library's flags without a device."""
+    from tests import user_estimators as U
+    t = P.register_estimator("cyl_cpu_test", U.CYLINDER_BODY)
+    assert t >= 8
+    with pytest.raises(P.ProcrayError, match="already registered"):
+        P.register_estimator("cyl_cpu_test", U.CYLINDER_BODY)
+    for bad in ("9abc", "", "a-b", "x" * 49):
+        with pytest.raises(P.ProcrayError, match="name"):
+            P.register_estimator(bad, U.CYLINDER_BODY)
+    with pytest.raises(P.ProcrayError, match="body"):
+        P.register_estimator("empty_body", "")
+    b = W._SceneBuilder()
+    m = b.material((0.5, 0.5, 0.5))
+    aabb, prm = U.cylinder_geom(0.5, 1.0)
+    b.instance(b.geometry((t, aabb, prm)), m, W.xform(np.eye(3), 1.0, (0, 0, 0)))
+    desc = b.build(light_pos=(2, 4, -3))
+    P.Scene(desc, build=False).close()
+    desc.geom_type = np.array([t + 7], np.uint32)
+    with pytest.raises(P.ProcrayError, match="unknown primitive type"):
+        P.Scene(desc, build=False)
+    P.build_estimators()
+
+
+def test_user_estimator_compile_error_is_reported(tmp_path):
+    """A body that does not compile fails pr_build_estimators with the
+    compiler's message (in a child process, so the registry of this one stays
+    valid)."""
+    import subprocess, sys, os
+    code = (
+        "import paper_2012_10357_amd as P\n"
+        "P.register_estimator('broken', 'return undeclared_thing + x;')\n"
+        "try:\n"
+        "    P.build_estimators()\n"
+        "    print('NO ERROR')\n"
+        "except P.ProcrayError as e:\n"
+        "    print('ERROR', e)\n")
+    env = dict(os.environ, PR_USER_CACHE=str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert "ERROR" in r.stdout and "INVALID_ARG" in r.stdout, r.stdout + r.stderr
+    assert "undeclared_thing" in r.stdout
