@@ -38,6 +38,7 @@ struct LaunchCtx {
   size_t graph_bytes = 0;
   int graph_blocks = 0, graph_budget = 0;
   hipStream_t graph_stream = nullptr;
+  const void* graph_kernel = nullptr;   // the kernel the graph launches (nullptr: built-in)
 };
 
 LaunchCtx* acquire_ctx(uint32_t n_req);

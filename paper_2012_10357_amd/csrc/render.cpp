@@ -399,8 +399,9 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   hipError_t e;
   bool graphed = false;
   if (use_graph && stream != nullptr && counts_dev == nullptr) {
+    const void* kernel_id = user ? uk.plain : nullptr;
     if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
-          c->graph_budget == step_budget && c->graph_stream == stream)) {
+          c->graph_budget == step_budget && c->graph_stream == stream && c->graph_kernel == kernel_id)) {
       if (c->graph) {
         hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
@@ -424,6 +425,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
         c->graph_blocks = cfg.grid_blocks;
         c->graph_budget = step_budget;
         c->graph_stream = stream;
+        c->graph_kernel = kernel_id;
       }
     }
     if (c->graph) {

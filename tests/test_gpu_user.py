@@ -83,3 +83,30 @@ def test_user_estimators_batch_counts_and_schedule():
     rgb = torch.empty((opts.height, opts.width, 3), device="cuda")
     c = P.render_counts(sc, cam, opts, rgb)
     assert int(c[28]) == opts.width * opts.height * opts.spp
+
+
+def test_graph_cache_tells_kernels_apart():
+    """A launch context that replayed a captured graph of the built-in kernel
+    must not replay it for a batch that needs the user-estimator kernel, even
+    with the same table size, grid, budget and stream."""
+    P = require_gpu()
+    import torch
+    types = _register(P)
+    user_sc = P.Scene(_scene(types))
+    teaser = P.Scene(W.c2_scene())
+    cam = W.camera((0.0, 1.2, -5.0))
+    opts = W.RenderOpts(256, 192, max_steps=256, shadows=1, bounces=1)
+    stream = torch.cuda.Stream()
+    a = alloc(256, 192)
+    ra = P.make_requests([(teaser, W.c2_camera(), opts, *a, 0)])
+    b = alloc(256, 192)
+    rb = P.make_requests([(user_sc, cam, opts, *b, 1)])
+    for _ in range(2):
+        P.render_batch(ra, tile=(8, 8), step_budget=16, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        P.render_batch(rb, tile=(8, 8), step_budget=16, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        want = gpu_render(P, user_sc, cam, opts)
+        got = tuple(x.cpu().numpy() for x in b)
+        for x, y in zip(want, got):
+            assert np.array_equal(x, y, equal_nan=True)
