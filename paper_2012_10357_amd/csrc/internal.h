@@ -92,7 +92,7 @@ struct alignas(16) ReqDev {
   const InstDev* insts;    // instance records, in BVH leaf order
   const NodeDev* nodes;
   const SceneConstsDev* consts;
-  const uint32_t* inst_id; // BVH slot -> user instance index
+  const void* reserved;    // unused (instance ids travel in the records)
   float* out_rgb;
   float* out_t;
   int32_t* out_inst;

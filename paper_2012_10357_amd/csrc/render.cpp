@@ -286,7 +286,6 @@ void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_rende
   r.insts = s->d_insts;
   r.nodes = s->d_nodes;
   r.consts = s->d_consts;
-  r.inst_id = nullptr;
   r.out_rgb = rgb;
   r.out_t = t;
   r.out_inst = inst;
