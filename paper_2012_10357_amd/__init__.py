@@ -120,6 +120,9 @@ assert C.sizeof(Geometry) == 76 and C.sizeof(Instance) == 56 and C.sizeof(Materi
 assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(RenderOptsC) == 64
 assert C.sizeof(BvhNode) == 32
 
+# The C ABI revision these ctypes layouts and signatures describe.
+PR_ABI_VERSION = 4
+
 _lib = None
 
 
@@ -165,6 +168,9 @@ def lib():
     L.pr_last_error.argtypes = []
     L.pr_abi_version.restype = C.c_uint32
     L.pr_device_count.restype = C.c_uint32
+    if L.pr_abi_version() != PR_ABI_VERSION:
+        raise ProcrayError(PR_ERR_UNSUPPORTED, f"{LIB_PATH} has ABI version {L.pr_abi_version()}, "
+                                               f"the binding expects {PR_ABI_VERSION}: rebuild")
     _lib = L
     return L
 
