@@ -245,3 +245,12 @@ def test_user_estimator_compile_error_is_reported(tmp_path):
                        cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert "ERROR" in r.stdout and "INVALID_ARG" in r.stdout, r.stdout + r.stderr
     assert "undeclared_thing" in r.stdout
+
+
+def test_binding_abi_version_matches_header(P):
+    """The binding's struct layouts are written for the header's ABI revision."""
+    import os, re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                            "procray.h")).read()
+    v = int(re.search(r"#define PR_ABI_VERSION (\d+)", hdr).group(1))
+    assert v == P.PR_ABI_VERSION == P.abi_version()
