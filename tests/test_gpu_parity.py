@@ -122,3 +122,20 @@ def test_all_types_scene_with_bounce():
     g = gpu_render(P, sc, cam, opts)
     orc = T.render(scene, cam, opts)
     _check(parity.compare(*flat(*g), orc, "all types + bounce"))
+
+
+def test_c1_against_golden_fixture():
+    """The GPU against the stored oracle values of tests/golden (no oracle
+    run at test time)."""
+    import os
+    P = require_gpu()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_16x12_oracle.txt")
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    orc = dict(inst=np.array([int(r[1]) for r in rows]), excl=np.array([int(r[2]) for r in rows]),
+               t=np.array([float(r[3]) for r in rows]),
+               rgb=np.array([[float(v) for v in r[4:7]] for r in rows]))
+    wl = W.c1(16, 12)
+    g = gpu_render(P, P.Scene(wl.scenes[0]), wl.requests[0].camera, wl.requests[0].opts)
+    rep = parity.compare(*flat(*g), orc, "c1 16x12 vs golden")
+    _check(rep)
+    assert rep["mask_all"] == 1.0
