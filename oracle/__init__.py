@@ -21,6 +21,12 @@ the sphere-traced fractals and CSG pac-men of the sample scene (Sec. 4,
 Figs. 4-6).  The paper gives no device code, so every formula is the textbook
 definition named in each function's docstring.
 
+Beyond the sample scene's primitives it follows the same definitions for
+primitives cut by a plane (CSG with a half-space, Fig. 5), triangle meshes
+placed by instance transforms (the plane of Fig. 4; closed-form hits) and
+estimators a test registers as NumPy functions (``de.register_estimator``,
+the twins of user estimators compiled into the kernel).
+
 Parity status per function is stated in the module headers; the quaternion
 Julia estimator at generic c and the Mandelbulb estimator off the polar axis
 are "parity unpinned" beyond the special cases and invariants checked in
