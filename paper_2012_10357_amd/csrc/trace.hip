@@ -882,48 +882,60 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       __builtin_amdgcn_s_setprio(0);
     }
 
+    // A cut is only set by the control phase, so one test per burst tells
+    // whether any marching lane of the wave needs it.
+    const bool wave_cut =
+        __ballot(has_job && mode == M_MARCH && cut_line[tid].x != -__builtin_inff()) != 0ull;
+    const int busy_n = __popcll(busy);
+
     // burst of lock-step estimator evaluations
     for (int it = 0; it < step_budget; ++it) {
-      const bool active = has_job && mode == M_MARCH;
-      if (active) {
+      if (has_job && mode == M_MARCH) {
         const float qx = lo_[0] + t * ld_[0];
         const float qy = lo_[1] + t * ld_[1];
         const float qz = lo_[2] + t * ld_[2];
-        int iters;
-        float de = cur_type == kTriangle ? 0.f : de_eval(cur_type, qx, qy, qz, prm, &iters);
-        const float2 cl = cut_line[tid];
-        if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
+        int iters = 0;
+        float de = 0.f;  // a triangle's hit was found in closed form: a zero estimate
+        if (cur_type != kTriangle) {
+          de = de_eval(cur_type, qx, qy, qz, prm, &iters);
+        }
+        if (wave_cut) {
+          const float2 cl = cut_line[tid];
+          if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
+        }
         ++job_evals;
         if constexpr (COUNT) if (cur_type < PR_NUM_TYPES) {
           atomicAdd(&cnt_lds[cur_type], 1ull);
           atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
         }
         const float v = sigma * de;
-        if (v < eps) {
-          // hit at t
-          if (kind & 1u) {
-            occluded = true;
-            mode = M_RAYDONE;
-          } else {
-            // closest hit: lexicographic minimum of (t, instance index)
-            const uint32_t u = __float_as_uint(inst_ptr(cur_slot)->prm[7]);
-            if (best_slot < 0 || t < limit || (t == limit && u < best_uid)) {
-              limit = t;
-              best_slot = cur_slot;
-              best_uid = u;
+        // the common case, a step, without branches; false for a hit and NaN
+        const bool step = v >= eps;
+        t = step ? t + v : t;
+        steps += step ? 1 : 0;
+        if (!step || t > t1 || steps >= (int)max_steps) {
+          if (v < eps) {
+            // hit at t
+            if (kind & 1u) {
+              occluded = true;
+              mode = M_RAYDONE;
+            } else {
+              // closest hit: lexicographic minimum of (t, instance index)
+              const uint32_t u = __float_as_uint(inst_ptr(cur_slot)->prm[7]);
+              if (best_slot < 0 || t < limit || (t == limit && u < best_uid)) {
+                limit = t;
+                best_slot = cur_slot;
+                best_uid = u;
+              }
+              mode = M_TRAVERSE;
             }
-            mode = M_TRAVERSE;
+          } else {
+            mode = M_TRAVERSE;  // left the box, out of steps, or NaN (a miss)
           }
-        } else if (!(v == v)) {
-          mode = M_TRAVERSE;   // NaN ends the march as a miss
-        } else {
-          t += v;
-          ++steps;
-          if (t > t1 || steps >= (int)max_steps) mode = M_TRAVERSE;
         }
       }
-      const int still = __popcll(__ballot(has_job && mode == M_MARCH));
-      if (still == 0 || 2 * still < __popcll(busy)) break;
+      // end the burst once fewer than half the busy lanes still march
+      if (2 * __popcll(__ballot(has_job && mode == M_MARCH)) < busy_n) break;
     }
   }
 
