@@ -934,8 +934,10 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
           }
         }
       }
-      // end the burst once fewer than half the busy lanes still march
-      if (2 * __popcll(__ballot(has_job && mode == M_MARCH)) < busy_n) break;
+      // end the burst once fewer than an eighth of the busy lanes still
+      // march: a control phase costs about as much as four steps, so lanes
+      // that have finished wait a few steps rather than being refilled
+      if (8 * __popcll(__ballot(has_job && mode == M_MARCH)) < busy_n) break;
     }
   }
 
