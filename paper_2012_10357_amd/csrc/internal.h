@@ -75,12 +75,14 @@ static_assert(sizeof(SceneConstsDev) == 64, "scene constants");
 
 // One render request as seen by the kernel.  192 bytes.  A job is one
 // (pixel, sample); jobs of a tile are ordered sample-major: tile, sample, lane.
+// The camera arrives as its orthonormal basis and pixel mapping, computed on
+// the host in double.
 struct alignas(16) ReqDev {
   float eye[3];
-  float vfov_deg;
-  float target[3];
+  float pix_kx;            // pixel pitch on the image plane at distance 1: 2 tan(vfov / 2) / H
+  float fwd[3];            // unit view direction
   uint32_t width;
-  float up[3];
+  float right[3];          // unit image-plane x axis (up x fwd, normalised)
   uint32_t height;
   uint32_t spp, jitter, max_steps, shadows;
   uint32_t bounces, seed_lo, seed_hi, tile_w;
@@ -92,7 +94,7 @@ struct alignas(16) ReqDev {
   const InstDev* insts;    // instance records, in BVH leaf order
   const NodeDev* nodes;
   const SceneConstsDev* consts;
-  const void* reserved;    // unused (instance ids travel in the records)
+  float pix_ky, pix_oy;    // -pix_kx and tan(vfov / 2): plane y of pixel row py is (py + jy) pix_ky + pix_oy
   float* out_rgb;
   float* out_t;
   int32_t* out_inst;

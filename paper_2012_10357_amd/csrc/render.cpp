@@ -257,12 +257,29 @@ void first_region(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_r
 void fill_req(ReqDev& r, const pr_scene* s, const pr_camera* cam, const pr_render_opts* o, uint32_t w,
               uint32_t h, uint32_t tile_w, float* rgb, float* t, int32_t* inst, uint32_t job_begin) {
   std::memset(&r, 0, sizeof r);
-  for (int i = 0; i < 3; ++i) {
-    r.eye[i] = cam->eye[i];
-    r.target[i] = cam->target[i];
-    r.up[i] = cam->up[i];
+  {
+    // camera basis and pixel mapping, in double, once per request
+    double f[3], rt[3];
+    for (int i = 0; i < 3; ++i) {
+      r.eye[i] = cam->eye[i];
+      f[i] = (double)cam->target[i] - cam->eye[i];
+    }
+    const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (double& v : f) v /= fl;
+    const double up[3] = {cam->up[0], cam->up[1], cam->up[2]};
+    rt[0] = up[1] * f[2] - up[2] * f[1];
+    rt[1] = up[2] * f[0] - up[0] * f[2];
+    rt[2] = up[0] * f[1] - up[1] * f[0];
+    const double rl = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    for (int i = 0; i < 3; ++i) {
+      r.fwd[i] = (float)f[i];
+      r.right[i] = (float)(rt[i] / rl);
+    }
+    const double sh = std::tan((double)cam->vfov_deg * M_PI / 360.0);
+    r.pix_kx = (float)(2.0 * sh / h);   // = 2 sh aspect / w
+    r.pix_ky = (float)(-2.0 * sh / h);
+    r.pix_oy = (float)sh;
   }
-  r.vfov_deg = cam->vfov_deg;
   r.width = w;
   r.height = h;
   r.spp = o->spp;

@@ -276,16 +276,9 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
 
   auto primary_ray = [&]() __attribute__((always_inline)) {
     const float ex = R->eye[0], ey = R->eye[1], ez = R->eye[2];
-    float fx = R->target[0] - ex, fy = R->target[1] - ey, fz = R->target[2] - ez;
-    float fl = 1.0f / __builtin_sqrtf(fx * fx + fy * fy + fz * fz);
-    fx *= fl; fy *= fl; fz *= fl;
-    const float ux0 = R->up[0], uy0 = R->up[1], uz0 = R->up[2];
-    float rx = uy0 * fz - uz0 * fy, ry = uz0 * fx - ux0 * fz, rz = ux0 * fy - uy0 * fx;
-    float rl = 1.0f / __builtin_sqrtf(rx * rx + ry * ry + rz * rz);
-    rx *= rl; ry *= rl; rz *= rl;
-    float ux = fy * rz - fz * ry, uy = fz * rx - fx * rz, uz = fx * ry - fy * rx;
-    const float W = (float)R->width, H = (float)R->height;
-    const float sh = tanf(R->vfov_deg * (3.14159265358979323846f / 360.0f));
+    const float fx = R->fwd[0], fy = R->fwd[1], fz = R->fwd[2];
+    const float rx = R->right[0], ry = R->right[1], rz = R->right[2];
+    const float ux = fy * rz - fz * ry, uy = fz * rx - fx * rz, uz = fx * ry - fy * rx;
     float jx = 0.5f, jy = 0.5f;
     if (R->spp != 1 || R->jitter) {
       uint32_t k0 = lowbias32(R->seed_lo ^ lowbias32(R->seed_hi));
@@ -293,8 +286,10 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       jx = (float)(lowbias32(k ^ 0xA511E9B3u) >> 8) * (1.0f / 16777216.0f);
       jy = (float)(lowbias32(k ^ 0x63D83595u) >> 8) * (1.0f / 16777216.0f);
     }
-    float sx = (2.0f * ((float)px + jx) / W - 1.0f) * sh * (W / H);
-    float sy = (1.0f - 2.0f * ((float)py + jy) / H) * sh;
+    // image-plane coordinates at distance 1 (x right, y up)
+    const float kx = R->pix_kx;
+    float sx = fmaf((float)px + jx, kx, -0.5f * kx * (float)R->width);
+    float sy = fmaf((float)py + jy, R->pix_ky, R->pix_oy);
     float dx = fx + sx * rx + sy * ux, dy = fy + sx * ry + sy * uy, dz = fz + sx * rz + sy * uz;
     float dl = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
     Ray r{ex, ey, ez, dx * dl, dy * dl, dz * dl};
