@@ -101,16 +101,24 @@ def _oracle_chunk(pix):
     return {"rays": out["counts"]["rays"]}
 
 
+# the kernel and the host code that sets its launch (grid, burst budget, tile
+# order, request records)
 KERNEL_SOURCES = ["paper_2012_10357_amd/csrc/trace.hip", "paper_2012_10357_amd/csrc/de.h",
-                  "paper_2012_10357_amd/csrc/internal.h"]
+                  "paper_2012_10357_amd/csrc/internal.h", "paper_2012_10357_amd/csrc/render.cpp"]
 TRAFFIC_PROFILE = "profiles/trace_kernel_teaser_1080p_pmc.md"
 
 
 def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) over the kernel sources with comments and
+    whitespace removed: the counters depend on the code, not on its comments."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        text = open(os.path.join(ROOT, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

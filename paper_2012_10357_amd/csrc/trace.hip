@@ -12,18 +12,22 @@
 // An optional single mirror bounce per primary hit is shaded the same way.
 //
 // Execution model (MI355X-native, not the paper's DXR pipeline):
-//  - one persistent grid fills the 256 CUs; each lane owns one pixel job
-//    (all of its samples) and runs it as a small state machine: traverse ->
-//    march -> normal -> shadow -> bounce -> ...;
+//  - one persistent grid fills the 256 CUs; each lane owns one job, a
+//    (pixel, sample), and runs it as a small state machine: traverse ->
+//    march -> normal -> shade -> shadow / bounce -> ...;
 //  - each loop iteration first refills idle lanes from a device job queue
-//    that spans every request of the launch (one wave-aggregated atomic per
-//    refill), then runs the divergent control work, then a burst of up to
-//    `step_budget` lock-step estimator evaluations for all lanes that are
-//    marching or evaluating a normal; the burst ends early once fewer than
-//    half of the lanes still need an evaluation, so finished lanes are
-//    re-used instead of idling (ballot-based regrouping);
+//    that spans every request of the launch (a wave reserves 64 consecutive
+//    jobs per queue atomic), then runs the divergent control work, then one
+//    pooled FP64 pass over the normal taps the wave's lanes are waiting for,
+//    then a burst of up to `step_budget` lock-step FP32 estimator
+//    evaluations for all marching lanes; the burst ends early once fewer
+//    than an eighth of the busy lanes still march, so finished lanes are
+//    re-used without paying a control phase every few steps;
+//  - the shadow ray of a primary hit that also bounces is handed to an idle
+//    lane of the same wave, so it runs beside the bounce chain;
 //  - BVH stacks live in LDS ([depth][lane] layout, conflict-free);
-//  - everything is FP32 VALU work; there is no dense contraction, so no MFMA.
+//  - the work is VALU arithmetic (FP32 march, FP64 normal taps); there is
+//    no dense contraction, so no MFMA.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
