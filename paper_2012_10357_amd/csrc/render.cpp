@@ -44,13 +44,13 @@ LaunchCtx* acquire_ctx(uint32_t n_req) {
     return nullptr;
   }
   if (hipHostMalloc(&c->host, c->bytes, hipHostMallocDefault) != hipSuccess) {
-    hipFree(c->dev);
+    (void)hipFree(c->dev);
     delete c;
     return nullptr;
   }
   if (hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
-    hipFree(c->dev);
-    hipHostFree(c->host);
+    (void)hipFree(c->dev);
+    (void)hipHostFree(c->host);
     delete c;
     return nullptr;
   }
@@ -344,8 +344,8 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     if (r.spp > 1 && !r.sample_acc) need_px += (size_t)r.width * r.height;
   if (need_px > c->sample_px_cap) {
     // grow while the context is idle
-    if (c->sample_acc) hipFree(c->sample_acc);
-    if (c->sample_cnt) hipFree(c->sample_cnt);
+    if (c->sample_acc) (void)hipFree(c->sample_acc);
+    if (c->sample_cnt) (void)hipFree(c->sample_cnt);
     c->sample_acc = nullptr;
     c->sample_cnt = nullptr;
     c->sample_px_cap = 0;
@@ -354,8 +354,8 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
         hipMemset(c->sample_acc, 0, need_px * 3 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->sample_cnt, 0, need_px * sizeof(uint32_t)) != hipSuccess) {
       (void)hipGetLastError();
-      if (c->sample_acc) hipFree(c->sample_acc);
-      if (c->sample_cnt) hipFree(c->sample_cnt);
+      if (c->sample_acc) (void)hipFree(c->sample_acc);
+      if (c->sample_cnt) (void)hipFree(c->sample_cnt);
       c->sample_acc = nullptr;
       c->sample_cnt = nullptr;
       release_ctx(c);
@@ -417,20 +417,23 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
           c->graph_budget == step_budget && c->graph_stream == stream && c->graph_kernel == kernel_id)) {
       if (c->graph) {
-        hipGraphExecDestroy(c->graph);
+        (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
       }
       hipGraph_t g = nullptr;
       e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        hipMemcpyAsync(c->dev, c->host, bytes, hipMemcpyHostToDevice, stream);
-        launch(nullptr, stream, cfg);
+        // a graph missing its copy or kernel would replay as a no-op: any
+        // failure while capturing discards it (the plain path runs instead)
+        hipError_t ce = hipMemcpyAsync(c->dev, c->host, bytes, hipMemcpyHostToDevice, stream);
+        const int le = ce == hipSuccess ? launch(nullptr, stream, cfg) : 1;
         e = hipStreamEndCapture(stream, &g);
+        if (e == hipSuccess && (ce != hipSuccess || le != 0)) e = ce != hipSuccess ? ce : hipErrorLaunchFailure;
       }
       if (e == hipSuccess && g) {
         e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
       }
+      if (g) (void)hipGraphDestroy(g);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         c->graph = nullptr;
@@ -462,10 +465,12 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
       return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
   }
+  // the scenes' last-use events guard their buffers against a rebuild while
+  // this launch may still read them, so a failed record is an error
   e = hipEventRecord(c->done, stream);
   for (pr_scene* s : scenes)
-    if (s->last_use) hipEventRecord(s->last_use, stream);
-  if (done_evt) hipEventRecord(done_evt, stream);
+    if (s->last_use && e == hipSuccess) e = hipEventRecord(s->last_use, stream);
+  if (done_evt && e == hipSuccess) e = hipEventRecord(done_evt, stream);
   release_ctx(c);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   return PR_OK;
@@ -553,7 +558,11 @@ pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_op
     unsigned long long* d = nullptr;
     hipError_t e = hipMalloc((void**)&d, sizeof(unsigned long long) * kNumCounts);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(counts)");
-    hipMemset(d, 0, sizeof(unsigned long long) * kNumCounts);
+    e = hipMemset(d, 0, sizeof(unsigned long long) * kNumCounts);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e, "hipMemset(counts)");
+    }
     {
       std::lock_guard<std::mutex> lk(s->mu);
       st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), false, d, nullptr, nullptr);
@@ -563,7 +572,7 @@ pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_op
       if (e == hipSuccess) e = hipMemcpy(counts, d, sizeof(unsigned long long) * kNumCounts, hipMemcpyDeviceToHost);
       if (e != hipSuccess) st = hip_fail(e, "counting render");
     }
-    hipFree(d);
+    (void)hipFree(d);
     return st == PR_OK ? ok() : st;
   } catch (...) {
     return set_error(PR_ERR_DEVICE, "unexpected exception");
@@ -606,9 +615,16 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
     hipStream_t st_ = nullptr;
     hipError_t e = hipStreamCreate(&st_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-    hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
+    hipEvent_t a = nullptr, b = nullptr;
+    auto cleanup = [&]() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      (void)hipStreamDestroy(st_);
+    };
+    if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "hipEventCreate");
+    }
     float best_ms = 1e30f;
     pr_batch_opts best{8, 8, 16, 0};
     for (uint32_t tw : tiles) {
@@ -617,20 +633,25 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
         // warm-up then 3 timed launches, take the minimum
         pr_status s = pr_render_batch(rq, n, &o, st_);
         if (s != PR_OK) {
-          hipEventDestroy(a);
-          hipEventDestroy(b);
-          hipStreamDestroy(st_);
+          cleanup();
           return s;
         }
         float ms_min = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
-          hipEventRecord(a, st_);
-          pr_render_batch(rq, n, &o, st_);
-          hipEventRecord(b, st_);
-          hipEventSynchronize(b);
+          if ((e = hipEventRecord(a, st_)) != hipSuccess) break;
+          if ((s = pr_render_batch(rq, n, &o, st_)) != PR_OK) {
+            cleanup();
+            return s;
+          }
           float ms = 0;
-          hipEventElapsedTime(&ms, a, b);
+          if ((e = hipEventRecord(b, st_)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess ||
+              (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess)
+            break;
           ms_min = std::min(ms_min, ms);
+        }
+        if (e != hipSuccess) {
+          cleanup();
+          return hip_fail(e, "timing a candidate launch");
         }
         if (ms_min < best_ms) {
           best_ms = ms_min;
@@ -638,9 +659,7 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
         }
       }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    hipStreamDestroy(st_);
+    cleanup();
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       load_tune_cache();

@@ -527,10 +527,10 @@ static bool scene_busy(pr_scene* s) {
 }
 
 static void free_device(pr_scene* s) {
-  if (s->d_insts) hipFree(s->d_insts);
-  if (s->d_nodes) hipFree(s->d_nodes);
-  if (s->d_consts) hipFree(s->d_consts);
-  if (s->d_shade) hipFree(s->d_shade);
+  if (s->d_insts) (void)hipFree(s->d_insts);
+  if (s->d_nodes) (void)hipFree(s->d_nodes);
+  if (s->d_consts) (void)hipFree(s->d_consts);
+  if (s->d_shade) (void)hipFree(s->d_shade);
   s->d_insts = nullptr;
   s->d_nodes = nullptr;
   s->d_consts = nullptr;
@@ -635,7 +635,7 @@ pr_status pr_scene_destroy(pr_scene* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (scene_busy(s)) return set_error(PR_ERR_BUSY, "renders of this scene are in flight");
     free_device(s);
-    if (s->last_use) hipEventDestroy(s->last_use);
+    if (s->last_use) (void)hipEventDestroy(s->last_use);
     s->last_use = nullptr;
   }
   delete s;

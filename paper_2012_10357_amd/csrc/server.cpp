@@ -141,7 +141,8 @@ class HipExecutor : public Executor {
   }
   char* pool_base() override { return pool_; }
   pr_status launch(int slot, std::vector<Ticket*>& batch) override {
-    hipSetDevice(dev_);
+    const hipError_t de = hipSetDevice(dev_);
+    if (de != hipSuccess) return hip_fail(de, "hipSetDevice");
     std::vector<ReqDev> reqs;
     std::vector<pr_scene*> scenes;
     uint32_t total = 0;
@@ -165,12 +166,12 @@ class HipExecutor : public Executor {
   }
   bool done(int slot) override { return hipEventQuery(events_[slot]) != hipErrorNotReady; }
   void shutdown() override {
-    for (auto s : streams_) hipStreamSynchronize(s);
-    for (auto e : events_) hipEventDestroy(e);
-    for (auto s : streams_) hipStreamDestroy(s);
+    for (auto s : streams_) (void)hipStreamSynchronize(s);
+    for (auto e : events_) (void)hipEventDestroy(e);
+    for (auto s : streams_) (void)hipStreamDestroy(s);
     streams_.clear();
     events_.clear();
-    if (pool_) hipFree(pool_);
+    if (pool_) (void)hipFree(pool_);
     pool_ = nullptr;
   }
 
