@@ -122,23 +122,34 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def committed_counters():
+    """Machine-readable figures of the committed counter profile (HBM bytes
+    per launch, VALU issue utilisation, active-lane fraction), if it was taken
+    on the current kernel source (else an empty dict)."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return {}
+    fields = {}
+    for line in open(path):
+        k, sep, v = line.partition(":")
+        if sep and k.strip() in ("kernel_source_sha256", "traffic_bytes_per_launch",
+                                 "valu_issue_utilisation", "active_lane_fraction"):
+            fields[k.strip()] = v.strip()
+    if fields.pop("kernel_source_sha256", None) != kernel_source_hash():
+        return {}
+    out = {}
+    for k, v in fields.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
 def committed_traffic():
     """HBM bytes per launch from the committed counter profile, if it was taken
     on the current kernel source (else None)."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if line.startswith("traffic_") or line.startswith("kernel_source_sha256"):
-            k, _, v = line.partition(":")
-            fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return committed_counters().get("traffic_bytes_per_launch")
 
 
 def bench_batched(P, W, torch, dev):
@@ -402,8 +413,12 @@ def main():
     print(f"# frame: {rays_per_frame} rays, {flops_per_frame / 1e9:.2f} GFLOP, "
           f"kernel {kern_ms:.3f} ms (min {per_launch_ms.min():.3f}), "
           f"{cus} CUs x {wg_per_cu} workgroups", file=sys.stderr, flush=True)
-    traffic = committed_traffic()
-    out["roofline"]["traffic"] = traffic
+    # HBM traffic and issue figures from the committed counter profile of this
+    # kernel source (null when the source has changed since it was taken)
+    counters = committed_counters()
+    out["roofline"]["traffic"] = counters.get("traffic_bytes_per_launch")
+    out["roofline"]["valu_issue_frac"] = counters.get("valu_issue_utilisation")
+    out["roofline"]["active_lane_frac"] = counters.get("active_lane_fraction")
     sc.close()
     if not args.no_batch:
         out["batched"] = bench_batched(P, W, torch, dev)
