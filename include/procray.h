@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 4
+#define PR_ABI_VERSION 5
 
 typedef enum {
   PR_OK = 0,
@@ -215,6 +215,30 @@ pr_status pr_register_estimator(const char* name, const char* body, uint32_t* ty
  * errors surface here rather than at the first render: PR_ERR_INVALID_ARG
  * with the compiler's message.  PR_OK when nothing is registered. */
 pr_status pr_build_estimators(void);
+
+/* The closest-hit half of a user hit group (the paper's hit groups pair an
+ * intersection routine with a closest-hit shader per geometry, Sec. 2.2.3,
+ * Eq. 1; listing "Hit group creation"): hits on instances of user type
+ * `type` (from pr_register_estimator) take their colour from this function
+ * instead of the built-in Lambert term; the blend with a mirror bounce stays
+ * built in.  `body` is HIP C++, the body of
+ *   void f(float px, float py, float pz,   world hit point
+ *          float nx, float ny, float nz,   unit world normal
+ *          float vx, float vy, float vz,   unit direction from the hit toward the ray's origin
+ *          float lx, float ly, float lz,   unit direction from the hit toward the light
+ *          float lit,                      1 if the shadow ray reached the light (or shadows
+ *                                          are off), else 0
+ *          const float* albedo,            the instance material's rgb
+ *          float ambient, const float* light_rgb,
+ *          const float* k,                 the geometry's params[0..6]
+ *          float* rgb)                     out: the hit's colour
+ * It must depend on its arguments only: it is evaluated for lit = 0 and
+ * lit = 1 before the shadow ray returns.  One per type; registering again
+ * replaces the body.  Built with the estimators (pr_build_estimators or the
+ * first render that needs them), with the same errors.  PR_ERR_INVALID_ARG
+ * for a type that is not a registered user type or a body that is empty or
+ * over 64 KiB; the body is copied. */
+pr_status pr_register_closest_hit(uint32_t type, const char* body);
 
 /* ---------------------------------------------------------------- rendering */
 

@@ -23,9 +23,10 @@ definition named in each function's docstring.
 
 Beyond the sample scene's primitives it follows the same definitions for
 primitives cut by a plane (CSG with a half-space, Fig. 5), triangle meshes
-placed by instance transforms (the plane of Fig. 4; closed-form hits) and
-estimators a test registers as NumPy functions (``de.register_estimator``,
-the twins of user estimators compiled into the kernel).
+placed by instance transforms (the plane of Fig. 4; closed-form hits), and
+estimators and closest-hit functions a test registers as NumPy functions
+(``de.register_estimator``, ``de.register_closest_hit``: the twins of the
+user hit groups compiled into the kernel).
 
 Parity status per function is stated in the module headers; the quaternion
 Julia estimator at generic c and the Mandelbulb estimator off the polar axis

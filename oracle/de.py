@@ -186,6 +186,17 @@ def register_estimator(gtype: int, fn) -> None:
     USER[int(gtype)] = fn
 
 
+# User closest-hit functions (the shading half of a hit group, Sec. 2.2.3):
+# type id -> function (hit points, unit normals, unit directions toward the
+# ray origins, unit directions toward the light, lit (0/1), albedo (m, 3),
+# ambient, light rgb (3,), params (m, 8)) -> colours (m, 3), float64.
+CLOSEST_HIT = {}
+
+
+def register_closest_hit(gtype: int, fn) -> None:
+    CLOSEST_HIT[int(gtype)] = fn
+
+
 def de_eval(gtype: int, p: np.ndarray, prm: np.ndarray):
     """Evaluate the estimator of one primitive type at points p (m, 3).
 

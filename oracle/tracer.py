@@ -47,6 +47,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import de as D
 from .de import de_eval, JULIA, MANDELBULB
 
 HIT, MISS_EXIT, MISS_BUDGET, MISS_NAN = 0, 1, 2, 3
@@ -653,6 +654,15 @@ def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow, extra_shift=None):
     ell = _normalize(prep.light[None, :] - p)
     lam = np.maximum(0.0, np.sum(n * ell, axis=1))
     c = prep.albedo[inst] * (prep.ambient + (V * lam)[:, None] * prep.light_rgb[None, :])
+    # hits on a user type with a closest-hit function take their colour from it
+    if D.CLOSEST_HIT and proc.any():
+        gt = np.full(hidx.size, -1, np.int64)
+        gt[proc] = prep.gtype[inst[proc]]
+        for ty, fn in D.CLOSEST_HIT.items():
+            sel = gt == ty
+            if sel.any():
+                c[sel] = np.asarray(fn(p[sel], n[sel], -d[hidx[sel]], ell[sel], V[sel], prep.albedo[inst[sel]],
+                                       float(prep.ambient), prep.light_rgb, prep.prm[inst[sel]]), np.float64)
     col[hidx] = c
     nrm[hidx] = n
     pw[hidx] = p

@@ -32,6 +32,7 @@ EXPORTS = [
     "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
     "pr_abi_version", "pr_device_count", "pr_launch_shape", "pr_register_estimator", "pr_build_estimators",
+    "pr_register_closest_hit",
 ]
 
 
@@ -121,7 +122,7 @@ assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(Rend
 assert C.sizeof(BvhNode) == 32
 
 # The C ABI revision these ctypes layouts and signatures describe.
-PR_ABI_VERSION = 4
+PR_ABI_VERSION = 5
 
 _lib = None
 
@@ -159,6 +160,7 @@ def lib():
         "pr_launch_shape": [C.POINTER(U32), C.POINTER(U32)],
         "pr_register_estimator": [C.c_char_p, C.c_char_p, C.POINTER(U32)],
         "pr_build_estimators": [],
+        "pr_register_closest_hit": [U32, C.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -399,6 +401,11 @@ def register_estimator(name: str, body: str) -> int:
     t = C.c_uint32(0)
     _check(lib().pr_register_estimator(name.encode(), body.encode(), C.byref(t)))
     return int(t.value)
+
+
+def register_closest_hit(gtype: int, body: str) -> None:
+    """pr_register_closest_hit: the shading half of a user hit group."""
+    _check(lib().pr_register_closest_hit(int(gtype), body.encode()))
 
 
 def build_estimators():

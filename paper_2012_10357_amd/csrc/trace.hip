@@ -236,6 +236,12 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
 
   // shading stash
   float sh_lam = 0.f, sh_ar = 0.f, sh_ag = 0.f, sh_ab = 0.f;     // current hit
+#ifdef PR_USER_ESTIMATORS
+  // a hit shaded by a user closest-hit function: its colour unlit in sh_a*,
+  // lit in sh_l* (the shadow ray's outcome selects one)
+  bool sh_user = false;
+  float sh_lr = 0.f, sh_lg = 0.f, sh_lb = 0.f;
+#endif
   float p_cr = 0.f, p_cg = 0.f, p_cb = 0.f, p_rho = 0.f;         // primary local colour, rho
   Ray bounce_ray;
   float hpx = 0.f, hpy = 0.f, hpz = 0.f, hnx = 0.f, hny = 0.f, hnz = 0.f;
@@ -586,7 +592,27 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     hpx = hx; hpy = hy; hpz = hz; hnx = nx; hny = ny; hnz = nz;
     if (kind == K_PRIMARY) p_rho = refl;
     const float off = R->shadow_offset;
-    if (kind == K_PRIMARY && R->shadows && R->bounces >= 1 && refl > 0.f) {
+#ifdef PR_USER_ESTIMATORS
+    // The type's closest-hit function, if one is registered, for both
+    // outcomes of the shadow ray; such a hit traces its own shadow ray.
+    sh_user = false;
+    if (I.type >= PR_USER_TYPE_BASE) {
+      float c0[3], c1[3];
+      const float lux = lx * ll, luy = ly * ll, luz = lz * ll;
+      if (user_shade(I.type, hx, hy, hz, nx, ny, nz, -ray.dx, -ray.dy, -ray.dz, lux, luy, luz, 0.f, mat,
+                     sc->ambient, sc->light_rgb, I.prm, c0)) {
+        user_shade(I.type, hx, hy, hz, nx, ny, nz, -ray.dx, -ray.dy, -ray.dz, lux, luy, luz, 1.f, mat,
+                   sc->ambient, sc->light_rgb, I.prm, c1);
+        sh_user = true;
+        sh_ar = c0[0]; sh_ag = c0[1]; sh_ab = c0[2];
+        sh_lr = c1[0]; sh_lg = c1[1]; sh_lb = c1[2];
+      }
+    }
+    const bool may_hand_off = !sh_user;
+#else
+    constexpr bool may_hand_off = true;
+#endif
+    if (may_hand_off && kind == K_PRIMARY && R->shadows && R->bounces >= 1 && refl > 0.f) {
       // hand the shadow ray to an idle lane and start the mirror bounce now
       tk_val[wv][0][lane] = hx + off * nx;
       tk_val[wv][1][lane] = hy + off * ny;
@@ -615,6 +641,14 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   };
 
   auto lambert = [&](float V, float& cr, float& cg, float& cb) __attribute__((always_inline)) {
+#ifdef PR_USER_ESTIMATORS
+    if (sh_user) {
+      cr = V > 0.f ? sh_lr : sh_ar;
+      cg = V > 0.f ? sh_lg : sh_ag;
+      cb = V > 0.f ? sh_lb : sh_ab;
+      return;
+    }
+#endif
     const float amb = sc->ambient;
     cr = sh_ar * (amb + V * sh_lam * sc->light_rgb[0]);
     cg = sh_ag * (amb + V * sh_lam * sc->light_rgb[1]);

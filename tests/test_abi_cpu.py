@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == P.PR_ABI_VERSION == 4
+    assert P.abi_version() == P.PR_ABI_VERSION == 5
     assert P.device_count() >= 0
 
 
@@ -203,8 +203,9 @@ def test_mesh_validation_and_bvh_items(P):
 
 def test_user_estimator_registration_and_build(P):
     """Registering validates the name and body and hands out types from
-    PR_USER_TYPE_BASE; scenes accept registered types only; the estimators
-    compile with the library's flags without a device."""
+    PR_USER_TYPE_BASE; scenes accept registered types only; closest-hit
+    functions attach to registered user types only; estimators and
+    closest-hit functions compile with the library's flags without a device."""
     from tests import user_estimators as U
     t = P.register_estimator("cyl_cpu_test", U.CYLINDER_BODY)
     assert t >= 8
@@ -224,6 +225,14 @@ def test_user_estimator_registration_and_build(P):
     desc.geom_type = np.array([t + 7], np.uint32)
     with pytest.raises(P.ProcrayError, match="unknown primitive type"):
         P.Scene(desc, build=False)
+    # closest-hit functions attach to registered user types only
+    for bad_type in (0, 7, t + 1, 1000):
+        with pytest.raises(P.ProcrayError, match="not a registered user type"):
+            P.register_closest_hit(bad_type, U.STRIPED_CH_BODY)
+    with pytest.raises(P.ProcrayError, match="body"):
+        P.register_closest_hit(t, "")
+    P.register_closest_hit(t, U.LAMBERT_CH_BODY)
+    P.register_closest_hit(t, U.STRIPED_CH_BODY)   # replaces the first
     P.build_estimators()
 
 

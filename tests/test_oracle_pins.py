@@ -773,3 +773,86 @@ def test_p18_mesh_placement_rigid_motion():
     assert (a["inst"] >= 1).sum() > 200
     assert np.array_equal(a["inst"], b["inst"])
     assert np.allclose(a["rgb"], b["rgb"], atol=1e-9)
+
+
+# --- P19: user closest-hit functions (the shading half of a hit group) -------
+
+def _user_sphere_np(p, prm):
+    return np.linalg.norm(p, axis=1) - prm[:, 0]
+
+
+def _user_sphere_scene(gtype, refl=0.0, occluder=False, plane=False):
+    b = W._SceneBuilder()
+    prm = np.zeros(8, np.float32)
+    prm[0], prm[1], prm[2] = 0.8, 0.25, 0.5      # radius, then two parameters the pins read back
+    g = b.geometry((gtype, [-0.81] * 3 + [0.81] * 3, prm))
+    b.instance(g, b.material((0.7, 0.4, 0.2), refl), W.xform(np.eye(3), 1.0, (0.0, 0.0, 0.0)))
+    if occluder:
+        g2 = b.geometry(W.geom_sphere(0.3))
+        b.instance(g2, b.material((0.5, 0.5, 0.5)), W.xform(np.eye(3), 1.0, (0.9, 1.6, -0.9)))
+    if plane:
+        b.mesh(W.QUAD_VERTICES, W.QUAD_INDICES, [(b.material((0.6, 0.6, 0.6), 0.3),
+                                                  W.xform(np.eye(3), 6.0, (0.0, -1.0, 0.0)))])
+    return b.build(light_pos=(2.0, 4.0, -3.0))
+
+
+def test_p19_closest_hit_restating_lambert_is_the_builtin_image():
+    """A closest-hit function that restates the built-in Lambert term gives the
+    built-in image bit for bit, with shadows (an occluder casts one on the
+    sphere), a reflective sphere and a triangle plane reflecting it."""
+    from tests import user_estimators as U
+    t_plain, t_ch = 300, 301
+    for t in (t_plain, t_ch):
+        D.register_estimator(t, _user_sphere_np)
+    D.register_closest_hit(t_ch, U.lambert_ch_np)
+    try:
+        cam = W.camera((0.5, 1.0, -4.0))
+        opts = W.RenderOpts(48, 40, max_steps=256, shadows=1, bounces=1)
+        a = T.render(_user_sphere_scene(t_plain, 0.4, True, True), cam, opts)
+        b = T.render(_user_sphere_scene(t_ch, 0.4, True, True), cam, opts)
+        assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["inst"], b["inst"])
+        assert np.sum(a["inst"] == 0) > 100
+    finally:
+        D.CLOSEST_HIT.pop(t_ch, None)
+
+
+def test_p19_closest_hit_arguments():
+    """Each argument a closest-hit function receives, read back as a colour on
+    primary hits of a user sphere (no shadows, no bounce): the hit point
+    (on the ray at the returned t), the unit normal (the sphere's, p / |p|,
+    up to the central difference's O(h^2)), the unit direction toward the
+    eye, the unit direction toward the light and the parameters."""
+    cam = W.camera((0.3, 0.4, -3.0))
+    opts = W.RenderOpts(40, 32, max_steps=256, shadows=0, bounces=0)
+    o, d = T.camera_rays(cam, opts, np.arange(40 * 32))
+    L = np.array([2.0, 4.0, -3.0])
+    pick = {
+        "p": lambda p_, n, v, l, lit, al, am, lr, k: p_,
+        "n": lambda p_, n, v, l, lit, al, am, lr, k: n,
+        "v": lambda p_, n, v, l, lit, al, am, lr, k: v,
+        "l": lambda p_, n, v, l, lit, al, am, lr, k: l,
+        "k": lambda p_, n, v, l, lit, al, am, lr, k: k[:, 0:3],
+    }
+    for i, (name, fn) in enumerate(pick.items()):
+        t = 310 + i
+        D.register_estimator(t, _user_sphere_np)
+        D.register_closest_hit(t, fn)
+        try:
+            out = T.render(_user_sphere_scene(t), cam, opts)
+        finally:
+            D.CLOSEST_HIT.pop(t, None)
+        hit = (out["inst"] == 0) & (out["excl"] == 0)
+        assert hit.sum() > 100
+        th = np.where(hit, out["t"], 0.0)
+        p = o + th[:, None] * d
+        want = {
+            "p": (p, 1e-12),
+            "n": (p / np.linalg.norm(p, axis=1, keepdims=True), 1e-6),
+            "v": (-d, 1e-12),
+            "l": ((L - p) / np.linalg.norm(L - p, axis=1, keepdims=True), 1e-12),
+            "k": (np.broadcast_to(np.float32([0.8, 0.25, 0.5]).astype(np.float64), p.shape), 0.0),
+        }[name]
+        assert np.max(np.abs(out["rgb"][hit] - want[0][hit])) <= want[1], name
+        # the hit point lies on the sphere within the march tolerance
+        if name == "p":
+            assert np.max(np.abs(np.linalg.norm(p[hit], axis=1) - 0.8)) < 2e-4

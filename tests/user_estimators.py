@@ -37,3 +37,45 @@ def octahedron_geom(s):
     prm = np.zeros(8, np.float32); prm[0] = s
     m = 0.01
     return [-s - m] * 3 + [s + m] * 3, prm
+
+
+# Closest-hit functions (the shading half of a user hit group), HIP C++ bodies
+# and NumPy twins.  The arguments: hit point p, unit normal n, unit direction
+# toward the ray origin v, unit direction toward the light l, lit (0/1),
+# albedo, ambient, light rgb, params k; out: rgb.
+
+# the built-in Lambert term, restated
+LAMBERT_CH_BODY = """
+  const float lam = fmaxf(0.f, nx * lx + ny * ly + nz * lz);
+  for (int c = 0; c < 3; ++c) rgb[c] = albedo[c] * (ambient + lit * lam * light_rgb[c]);
+"""
+
+
+def lambert_ch_np(p, n, v, l, lit, albedo, ambient, light_rgb, k):
+    lam = np.maximum(0.0, np.sum(n * l, axis=1))
+    return albedo * (ambient + (lit * lam)[:, None] * light_rgb[None, :])
+
+
+# stripes across world y on the albedo, Lambert, a Blinn-Phong highlight
+# (exponent 16) and a term from the geometry's first parameter
+STRIPED_CH_BODY = """
+  const float stripe = 0.6f + 0.4f * cosf(6.f * py);
+  const float lam = fmaxf(0.f, nx * lx + ny * ly + nz * lz);
+  const float hx = lx + vx, hy = ly + vy, hz = lz + vz;
+  const float hl = sqrtf(hx * hx + hy * hy + hz * hz);
+  const float sp = hl > 0.f ? fmaxf(0.f, (nx * hx + ny * hy + nz * hz) / hl) : 0.f;
+  const float s2 = sp * sp, s4 = s2 * s2, s8 = s4 * s4, s16 = s8 * s8;
+  for (int c = 0; c < 3; ++c)
+    rgb[c] = stripe * albedo[c] * (ambient + lit * lam * light_rgb[c]) + lit * 0.5f * s16 * light_rgb[c] +
+             0.1f * k[0];
+"""
+
+
+def striped_ch_np(p, n, v, l, lit, albedo, ambient, light_rgb, k):
+    stripe = 0.6 + 0.4 * np.cos(6.0 * p[:, 1])
+    lam = np.maximum(0.0, np.sum(n * l, axis=1))
+    h = l + v
+    hl = np.linalg.norm(h, axis=1)
+    sp = np.where(hl > 0.0, np.maximum(0.0, np.sum(n * h, axis=1) / np.where(hl > 0.0, hl, 1.0)), 0.0)
+    return (stripe[:, None] * albedo * (ambient + (lit * lam)[:, None] * light_rgb[None, :])
+            + (lit * 0.5 * sp ** 16)[:, None] * light_rgb[None, :] + 0.1 * k[:, 0:1])
