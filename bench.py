@@ -76,9 +76,14 @@ def cpu_baseline(target_s=15.0):
     # calibrate on a small sample, then size the sample for ~target_s of wall time
     pix0 = W.pixel_sample(1920, 1080, 800, seed=101)
     t0 = time.perf_counter()
-    r0 = _oracle_chunk(pix0)
+    _oracle_chunk(pix0)
     dt0 = time.perf_counter() - t0
     rate = pix0.size / max(dt0, 1e-3)
+    # one core: a fresh sample sized for about 2 s in this process
+    pix1 = W.pixel_sample(1920, 1080, int(max(500, rate * 2.0)), seed=103)
+    t0 = time.perf_counter()
+    r1 = _oracle_chunk(pix1)
+    one_core = sum(r1["rays"].values()) / (time.perf_counter() - t0) / 1e6
     n = int(min(1920 * 1080, max(2000, rate * target_s * cores * 0.8)))
     pix = W.pixel_sample(1920, 1080, n, seed=102)
     chunks = np.array_split(pix, cores * 4)
@@ -89,7 +94,18 @@ def cpu_baseline(target_s=15.0):
     rays = sum(sum(r["rays"].values()) for r in res)
     return {"value": rays / wall / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded pixels of the 1920x1080 teaser frame (all their rays), "
-                      f"FP64 NumPy oracle in {cores} processes, {wall:.1f} s wall"}
+                      f"FP64 NumPy oracle in {cores} processes, {wall:.1f} s wall",
+            "one_core_value": round(one_core, 4), "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _oracle_chunk(pix):
