@@ -69,13 +69,15 @@ def test_user_estimators_full_frame():
     assert set(np.unique(g[2])) >= {0, 1, 2, 3, 4}
 
 
-def test_user_estimators_batch_counts_and_schedule():
+@pytest.mark.parametrize("cyl", ["cyl", "cyl_ch"])
+def test_user_estimators_batch_counts_and_schedule(cyl):
     """Batched with a built-in-only request, graph-captured, other tile and
-    budget: bitwise equal to single renders; the instrumented build runs too."""
+    budget: bitwise equal to single renders; the instrumented build runs too
+    (user estimators alone, and with a user closest-hit function)."""
     P = require_gpu()
     import torch
     types = _register(P)
-    scene = _scene(types)
+    scene = _scene(types, cyl)
     sc = P.Scene(scene)
     teaser = P.Scene(W.c2_scene())
     cam = W.camera((1.0, 2.0, -4.5), (0.0, -0.2, 0.0))
