@@ -263,3 +263,30 @@ def test_binding_abi_version_matches_header(P):
                             "procray.h")).read()
     v = int(re.search(r"#define PR_ABI_VERSION (\d+)", hdr).group(1))
     assert v == P.PR_ABI_VERSION == P.abi_version()
+
+
+def _depth(first, count, i=0):
+    return 1 if count[i] > 0 else 1 + max(_depth(first, count, first[i]), _depth(first, count, first[i] + 1))
+
+
+def test_scene_size_limit_and_bvh_depth(P):
+    """A scene holds at most 16384 items (16-bit traversal stack entries); at
+    that size the BVH stays within the depth the LDS stack allows, also when
+    every instance sits at the same place (no SAH split possible), and one
+    instance more is rejected before any device work."""
+    import sys
+    sys.setrecursionlimit(10000)
+    rng = np.random.default_rng(11)
+    full = W.random_instances_scene(rng, 16384, ["sphere", "torus"])
+    stacked = W.random_instances_scene(rng, 16384, ["sphere"])
+    stacked.inst_xform = np.tile(np.float32([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]), (16384, 1))
+    for desc in (full, stacked):
+        sc = P.Scene(desc, build=False)
+        sc.build(P.BvhOpts(32, 1, 1.0, 4.0, P.PR_BVH_HOST_ONLY))
+        lo, hi, first, count, order = sc.bvh()
+        assert sorted(order.tolist()) == list(range(16384))
+        assert _depth(first, count) <= 30
+        sc.close()
+    over = W.random_instances_scene(rng, 16385, ["sphere"])
+    with pytest.raises(P.ProcrayError, match="n_inst must be in 1..16384"):
+        P.Scene(over, build=False)

@@ -72,6 +72,21 @@ def test_c3_1080p_4spp_sampled():
     _check(parity.compare(*flat(*g, pixels=pix), orc, "c3 1080p 4spp sampled"))
 
 
+def test_max_instances_sampled():
+    """A scene at the item limit (16384 instances of two kinds, shadows),
+    320x180 on the GPU against the oracle on a seeded pixel sample."""
+    P = require_gpu()
+    rng = np.random.default_rng(7)
+    scene = W.random_instances_scene(rng, 16384, ["sphere", "torus"])
+    cam = W.camera((0.0, 0.0, -45.0))
+    opts = W.RenderOpts(320, 180, max_steps=256, shadows=1, bounces=0)
+    g = gpu_render(P, P.Scene(scene), cam, opts)
+    assert np.isfinite(g[0]).all()
+    pix = W.pixel_sample(320, 180, 700, seed=13)
+    orc = T.render(scene, cam, opts, pixels=pix)
+    _check(parity.compare(*flat(*g, pixels=pix), orc, "16384 instances 320x180 sampled"))
+
+
 @pytest.mark.parametrize("wh", [(1, 1), (1, 97), (130, 1), (65, 3)])
 def test_degenerate_and_ragged_sizes(wh):
     P = require_gpu()
