@@ -87,6 +87,27 @@ def test_max_instances_sampled():
     _check(parity.compare(*flat(*g, pixels=pix), orc, "16384 instances 320x180 sampled"))
 
 
+@pytest.mark.parametrize("wh", [(16384, 3), (5, 16384)])
+def test_max_image_side_sampled(wh):
+    """Images at the largest side the boundary accepts (16384), with ragged
+    tiles the other way, against the oracle on a seeded pixel sample."""
+    P = require_gpu()
+    w, h = wh
+    wl = W.c2(w, h)
+    scene, req = wl.scenes[0], wl.requests[0]
+    g = gpu_render(P, P.Scene(scene), req.camera, req.opts)
+    assert np.isfinite(g[0]).all()
+    # plus the middle of the frame, where the scene's objects are (a few
+    # columns wide at 16384 x 3)
+    cx, cy = w // 2, h // 2
+    mid = [y * w + x for y in range(max(0, cy - 24), min(h, cy + 25)) for x in range(max(0, cx - 24), min(w, cx + 25))]
+    pix = np.union1d(W.pixel_sample(w, h, 1200, seed=17), np.array(mid, np.int64))
+    orc = T.render(scene, req.camera, req.opts, pixels=pix)
+    rep = parity.compare(*flat(*g, pixels=pix), orc, f"max side {wh} sampled")
+    _check(rep)
+    assert rep["hit_frac"] > 0
+
+
 @pytest.mark.parametrize("wh", [(1, 1), (1, 97), (130, 1), (65, 3)])
 def test_degenerate_and_ragged_sizes(wh):
     P = require_gpu()
