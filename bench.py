@@ -269,13 +269,13 @@ def bench_next(P, W, torch, dev):
     return out
 
 
-def bench_served(P, W, torch, dev, seconds):
-    """Open-loop Poisson trace at 200 req/s over 8 resident scenes: the
-    continuous-batching server vs FIFO per-request pr_render launches."""
+def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
+    """Open-loop Poisson trace (200 req/s by default) over 8 resident scenes:
+    the continuous-batching server vs FIFO per-request pr_render launches."""
     import threading
     scenes = [P.Scene(s) for s in W.c5_scenes()]
-    n_req = max(20, int(200 * seconds))
-    reqs = W.c5_requests(n_req)
+    n_req = max(20, int(rate_hz * seconds))
+    reqs = W.c5_requests(n_req, rate_hz=rate_hz)
     prim_rays = sum(r.opts.width * r.opts.height * r.opts.spp for r in reqs)
 
     # --- server
@@ -341,7 +341,7 @@ def bench_served(P, W, torch, dev, seconds):
     fifo = {"p50_ms": round(float(np.percentile(lat_f, 50)) * 1e3, 2),
             "p99_ms": round(float(np.percentile(lat_f, 99)) * 1e3, 2),
             "primary_mrays_s": round(prim_rays / span_f / 1e6, 2)}
-    return {"requests": n_req, "rate_hz": 200, "trace_s": round(reqs[-1].arrival_s, 2),
+    return {"requests": n_req, "rate_hz": rate_hz, "trace_s": round(reqs[-1].arrival_s, 2),
             "server": served, "fifo_plain": fifo}
 
 
@@ -442,6 +442,10 @@ def main():
     if not args.no_served:
         out["served"] = bench_served(P, W, torch, dev, args.served_seconds)
         print(f"# served: {out['served']}", file=sys.stderr, flush=True)
+        # the same requests at half the rate, below the GPU's capacity: the
+        # latency of batching and execution rather than of a growing queue
+        out["served_100hz"] = bench_served(P, W, torch, dev, args.served_seconds, rate_hz=100.0)
+        print(f"# served at 100 req/s: {out['served_100hz']}", file=sys.stderr, flush=True)
     if not args.no_next:
         out["next"] = bench_next(P, W, torch, dev)
         print(f"# next: {out['next']}", file=sys.stderr, flush=True)
