@@ -160,6 +160,25 @@ def test_all_types_scene_with_bounce():
     _check(parity.compare(*flat(*g), orc, "all types + bounce"))
 
 
+@pytest.mark.parametrize("eye_z", [3.0, -3.0])
+def test_mandelbulb_down_its_polar_axis(eye_z):
+    """A Mandelbulb seen along its polar axis, odd image size: the central
+    rays run on or within rounding of the axis, where the azimuth of the map
+    is undefined and the orbit follows the real recurrence z <- |z|^8 + c."""
+    P = require_gpu()
+    b = W._SceneBuilder()
+    gi = b.geometry(W.geom_mandelbulb(8, 10, 2.0))
+    b.instance(gi, b.material((0.8, 0.6, 0.4), 0.3), W.xform(np.eye(3), 1.0, (0, 0, 0)))
+    scene = b.build(light_pos=(2, 5, 4 * np.sign(eye_z)))
+    cam = W.camera((0, 0, eye_z), (0, 0, 0), vfov_deg=30)
+    opts = W.RenderOpts(33, 33, spp=1, max_steps=256, eps=1e-4, tmax=100.0, shadows=1, bounces=1)
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, opts)
+    assert g[2][16, 16] >= 0                      # the axis ray hits
+    orc = T.render(scene, cam, opts)
+    _check(parity.compare(*flat(*g), orc, f"mandelbulb polar axis, eye z {eye_z}"))
+
+
 def test_c1_against_golden_fixture():
     """The GPU against the stored oracle values of tests/golden (no oracle
     run at test time)."""
