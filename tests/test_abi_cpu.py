@@ -104,6 +104,16 @@ def test_render_argument_errors_before_device(P):
     # host-only build: not uploaded, so rendering is refused before any device call
     with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
         P.render(sc, cam, o, fake)
+    # batches: empty, more than 4096 requests, a tile that is not 64 pixels,
+    # and a request whose scene is not on the device (named by its index)
+    one = P.make_requests([(sc, cam, o, fake, None, None, 0)])
+    L = P.lib()
+    assert L.pr_render_batch(one, 0, None, None) == P.PR_ERR_INVALID_ARG
+    assert L.pr_render_batch(one, 4097, None, None) == P.PR_ERR_INVALID_ARG
+    assert L.pr_autotune(one, 0, C.byref(P.BatchOpts())) == P.PR_ERR_INVALID_ARG
+    assert L.pr_render_batch(one, 1, C.byref(P.BatchOpts(8, 4, 0, 0)), None) == P.PR_ERR_INVALID_ARG
+    with pytest.raises(P.ProcrayError, match="request 0"):
+        P.render_batch(one)
     sc.close()
 
 
