@@ -16,7 +16,10 @@ iterations counted per launch times a fixed per-evaluation flop table
 (below) -- over its average duration measured with HIP events on the launch
 stream; ``cpu_baseline`` times the FP64 oracle on a bounded pixel sample.
 Optional sub-objects time the batched form (64 requests in one persistent
-launch vs 64 plain launches) and the served form (Poisson arrivals).
+launch vs 64 plain launches), the served form (Poisson arrivals), and the
+next-step workloads: the sample scene with its triangle plane, the cut Julia
+set, the Mandelbulb animation, and the teaser with its pac-men as a user hit
+group.
 """
 from __future__ import annotations
 
@@ -269,6 +272,57 @@ def bench_next(P, W, torch, dev):
     return out
 
 
+# A programmable hit group over the teaser frame: the two pac-men as a user
+# type whose estimator and closest-hit function are HIP C++ source compiled
+# into the trace kernel at run time (parameters R, cos a, sin a of the wedge
+# half-angle a), shaded by a restated Lambert term.
+F3_PACMAN_BODY = """
+  const R ca = (R)p[1], sa = (R)p[2];
+  const R len = sqrt(x * x + y * y + z * z);
+  const R qy = fabs(y);
+  const R qn = ca * qy - sa * x, qu = ca * x + sa * qy;
+  const R w = (qn > (R)0 && qu < (R)0) ? sqrt(x * x + qy * qy) : qn;
+  return fmax(len - (R)p[0], -w);
+"""
+F3_LAMBERT_BODY = """
+  const float lam = fmaxf(0.f, nx * lx + ny * ly + nz * lz);
+  for (int c = 0; c < 3; ++c) rgb[c] = albedo[c] * (ambient + lit * lam * light_rgb[c]);
+"""
+
+
+def f3_scene(W, gtype):
+    """The teaser scene with its pac-man geometry given as the user type."""
+    import dataclasses
+    s = W.c2_scene()
+    sel = s.geom_type == W.PACMAN
+    prm = s.geom_params.copy()
+    half = prm[sel, 1].astype(np.float64)
+    prm[sel, 1] = np.cos(half)
+    prm[sel, 2] = np.sin(half)
+    return dataclasses.replace(s, geom_type=np.where(sel, np.uint32(gtype), s.geom_type).astype(np.uint32),
+                               geom_params=prm)
+
+
+def bench_f3(P, W, torch, dev):
+    """The teaser frame with its pac-men as a user hit group, beside the same
+    frame with the built-in pac-man, timed alike (kernel time per frame)."""
+    base = P.Scene(W.c2_scene())
+    builtin = _frame_rate(P, torch, dev, base, W.c2_camera(), W.c2_opts())
+    base.close()
+    t0 = time.monotonic()
+    gtype = P.register_estimator("bench_user_pacman", F3_PACMAN_BODY)
+    P.register_closest_hit(gtype, F3_LAMBERT_BODY)
+    sc = P.Scene(f3_scene(W, gtype))
+    rgb = torch.empty((1080, 1920, 3), dtype=torch.float32, device=dev)
+    P.render(sc, W.c2_camera(), W.c2_opts(), rgb)      # builds the kernel with the user code
+    torch.cuda.synchronize()
+    build_s = time.monotonic() - t0
+    user = _frame_rate(P, torch, dev, sc, W.c2_camera(), W.c2_opts())
+    sc.close()
+    return {"ms": user["ms"], "mrays_s": user["mrays_s"], "rays": user["rays"],
+            "builtin_ms": builtin["ms"], "builtin_rays": builtin["rays"], "first_build_s": round(build_s, 1)}
+
+
 def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
     """Open-loop Poisson trace (200 req/s by default) over 8 resident scenes:
     the continuous-batching server vs FIFO per-request pr_render launches."""
@@ -449,6 +503,9 @@ def main():
     if not args.no_next:
         out["next"] = bench_next(P, W, torch, dev)
         print(f"# next: {out['next']}", file=sys.stderr, flush=True)
+        # last on the GPU: registering a user type builds a second kernel
+        out["next"]["teaser_user_pacmen_1080p"] = bench_f3(P, W, torch, dev)
+        print(f"# user hit group: {out['next']['teaser_user_pacmen_1080p']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -5,6 +5,7 @@ oracle running NumPy twins of the same functions."""
 import numpy as np
 import pytest
 
+import bench
 import workloads as W
 from oracle import de as D
 from oracle import tracer as T
@@ -28,6 +29,12 @@ def _register(P):
         _types["cyl_lam"] = P.register_estimator("gpu_test_cylinder_lambert", U.CYLINDER_BODY)
         P.register_closest_hit(_types["cyl_ch"], U.STRIPED_CH_BODY)
         P.register_closest_hit(_types["cyl_lam"], U.LAMBERT_CH_BODY)
+        # the benchmark's user hit group: the teaser's pac-man and Lambert shading restated
+        _types["pac"] = P.register_estimator("gpu_test_user_pacman", bench.F3_PACMAN_BODY)
+        P.register_closest_hit(_types["pac"], bench.F3_LAMBERT_BODY)
+        D.register_estimator(_types["pac"],
+                             lambda p, k: D.de_pacman(p, k[:, 0], np.arctan2(k[:, 2], k[:, 1])))
+        D.register_closest_hit(_types["pac"], U.lambert_ch_np)
         for k in ("cyl", "cyl_ch", "cyl_lam"):
             D.register_estimator(_types[k], U.cylinder_np)
         D.register_estimator(_types["oct"], U.octahedron_np)
@@ -159,3 +166,22 @@ def test_closest_hit_restating_lambert_matches_builtin():
     b = gpu_render(P, P.Scene(_scene(types, "cyl_lam")), cam, opts)
     assert np.array_equal(a[2], b[2])
     assert np.max(np.abs(a[0] - b[0])) < 1e-5
+
+
+def test_user_pacmen_teaser_against_oracle_and_builtin():
+    """The benchmark's user-hit-group frame -- the teaser with its pac-men as a
+    user type restating the built-in estimator and Lambert shading -- against
+    the oracle (running the built-in pac-man as the twin), and against the
+    built-in frame: the same pixels hit the same instances."""
+    P = require_gpu()
+    types = _register(P)
+    scene = bench.f3_scene(W, types["pac"])
+    cam, opts = W.c2_camera(), W.c2_opts(200, 113)
+    g = gpu_render(P, P.Scene(scene), cam, opts)
+    orc = T.render(scene, cam, opts)
+    rep = parity.compare(*flat(*g), orc, "teaser with user pac-men 200x113")
+    print(parity.fmt(rep), flush=True)
+    assert rep["pass"], parity.fmt(rep)
+    gb = gpu_render(P, P.Scene(W.c2_scene()), cam, opts)
+    assert np.mean(g[2] == gb[2]) >= 0.999
+    assert set(np.unique(g[2])) >= {0, 1, 2, 3}
