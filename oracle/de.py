@@ -27,10 +27,14 @@ defers their device code to a separate chapter):
 
 Parity: sphere, box, torus, box-frame and pac-man are pinned by closed-form
 ray intersections and the distance lower-bound invariant; the Julia estimator
-is pinned at c = 0 (exactly |p| ln|p| / 2) and at real c (complex Julia);
-the Mandelbulb on its polar axis (real recurrence |x|^P + c) and by its
-(P-1)-fold rotational and mirror symmetries.  Generic quaternion c and
-off-axis Mandelbulb points are parity unpinned beyond those invariants.
+is pinned at c = 0 (exactly |p| ln|p| / 2), at real c (complex Julia), and at
+generic quaternion c by the complex planes span{1, u} that its orbits keep
+(real axis; the plane of (c1, c2) when c3 = 0), by its invariance under
+rotations of the imaginary part and by the 2x2 complex matrix representation
+of the quaternions; the Mandelbulb on its polar axis (real recurrence
+|x|^P + c), by its (P-1)-fold rotational and mirror symmetries and by the
+agreement of its trigonometric and algebraic power maps.  Off-axis Mandelbulb
+points are parity unpinned beyond those invariants.
 """
 from __future__ import annotations
 

@@ -146,3 +146,26 @@ def real_bulb_axis_de(x, c, n_iter, bailout, power=8):
         z = r ** power + c
     r = abs(z)
     return 0.5 * math.log(r) * r / dr
+
+
+def quaternion_matrix_julia_de(p, c, n_iter, bailout):
+    """Quaternion Julia estimator computed in the 2x2 complex matrix
+    representation of the quaternions: a + b i + c j + d k is the matrix
+    [[a + b i, c + d i], [-c + d i, a - b i]], quaternion products are
+    matrix products and |q|^2 = det(Q).  The orbit Z <- Z Z + C starts at
+    the slice point (p_x, p_y, p_z, 0); the derivative m <- 2 |Z| m and the
+    escape and estimator rules are those of the quaternion definition."""
+    def mat(a, b, cc, d):
+        return np.array([[complex(a, b), complex(cc, d)], [complex(-cc, d), complex(a, -b)]])
+
+    Z = mat(p[0], p[1], p[2], 0.0)
+    C = mat(*c)
+    m = 1.0
+    for _ in range(n_iter):
+        r = math.sqrt(max(np.linalg.det(Z).real, 0.0))
+        if r > bailout:
+            break
+        m = 2.0 * r * m
+        Z = Z @ Z + C
+    r = math.sqrt(max(np.linalg.det(Z).real, 0.0))
+    return 0.5 * r * math.log(r) / m

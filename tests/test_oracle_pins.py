@@ -286,6 +286,111 @@ def test_p7_julia_real_c_axis_hit_converges_to_beta():
     assert max(errs) < 5e-6
 
 
+# P7b: the Julia estimator at a generic quaternion c (all four components
+# non-zero).  The quaternion square (x, v)^2 = (x^2 - |v|^2, 2 x v) commutes
+# with every orthogonal map of the imaginary part v, and for a unit imaginary
+# u the plane span{1, u} is a copy of the complex numbers (u^2 = -1).  So:
+#  (a) on the real axis the orbit of x stays in span{1, u_c}, u_c = c_im/|c_im|,
+#      and the estimator is the complex one at x with c0 + i|c_im|;
+#  (b) with c3 = 0 the orbit of x + s u_c (a point of the w = 0 slice) stays
+#      in that plane: the complex estimator at x + i s;
+#  (c) rotating (p_y, p_z) and (c1, c2) together about the x axis, or
+#      negating c3, leaves the estimator unchanged;
+#  (d) in the 2x2 complex matrix representation (an independent route
+#      through the algebra) the estimator agrees at generic points.
+# Each check fails for c entering with a wrong sign, in a wrong component or
+# not at all (see the planted-mistake test below).
+
+def _generic_cs(seed, n=6):
+    rng = np.random.default_rng(seed)
+    cs = rng.uniform(0.15, 0.8, (n, 4)) * rng.choice([-1.0, 1.0], (n, 4))
+    return cs
+
+
+def _julia_ref_ok(vals, refs):
+    # points whose orbit grazes the bailout radius may take one more or one
+    # fewer iteration under rounding; they are rare and dropped
+    return np.isfinite(vals) & np.isfinite(refs)
+
+
+def _check_axis(de_fn, c):
+    xs = np.linspace(-1.9, 1.9, 381)
+    p = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], 1)
+    de = de_fn(p, c)
+    cz = complex(c[0], math.sqrt(c[1] ** 2 + c[2] ** 2 + c[3] ** 2))
+    ref = np.array([AN.complex_julia_de(complex(x, 0.0), cz, 12, 4.0) for x in xs])
+    ok = _julia_ref_ok(de, ref)
+    return ok.sum() > 300 and np.allclose(de[ok], ref[ok], rtol=1e-9, atol=1e-12)
+
+
+def _check_plane(de_fn, c, seed=11):
+    c = np.array([c[0], c[1], c[2], 0.0])
+    u = np.array([c[1], c[2]]) / math.hypot(c[1], c[2])
+    rng = np.random.default_rng(seed)
+    xs, ss = rng.uniform(-1.8, 1.8, 300), rng.uniform(-1.8, 1.8, 300)
+    p = np.stack([xs, ss * u[0], ss * u[1]], 1)
+    de = de_fn(p, c)
+    cz = complex(c[0], math.hypot(c[1], c[2]))
+    ref = np.array([AN.complex_julia_de(complex(x, s), cz, 12, 4.0) for x, s in zip(xs, ss)])
+    ok = _julia_ref_ok(de, ref)
+    return ok.sum() > 280 and np.allclose(de[ok], ref[ok], rtol=1e-9, atol=1e-12)
+
+
+def _check_rotation(de_fn, c, seed=12):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-1.6, 1.6, (300, 3))
+    th = rng.uniform(0.3, 2.8)
+    ct, st = math.cos(th), math.sin(th)
+    rot = lambda a, b: (ct * a - st * b, st * a + ct * b)
+    py, pz = rot(p[:, 1], p[:, 2])
+    c1, c2 = rot(c[1], c[2])
+    de0 = de_fn(p, c)
+    de1 = de_fn(np.stack([p[:, 0], py, pz], 1), np.array([c[0], c1, c2, c[3]]))
+    de2 = de_fn(p, np.array([c[0], c[1], c[2], -c[3]]))
+    return (np.allclose(de0, de1, rtol=1e-9, atol=1e-12) and
+            np.allclose(de0, de2, rtol=1e-9, atol=1e-12))
+
+
+def _check_matrix(de_fn, c, seed=13):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-1.6, 1.6, (200, 3))
+    de = de_fn(p, c)
+    ref = np.array([AN.quaternion_matrix_julia_de(q, c, 12, 4.0) for q in p])
+    ok = _julia_ref_ok(de, ref)
+    return ok.sum() > 190 and np.allclose(de[ok], ref[ok], rtol=1e-9, atol=1e-12)
+
+
+def _oracle_julia(p, c):
+    return D.de_julia(p, np.asarray(c, np.float64), 12, 4.0)[0]
+
+
+@pytest.mark.parametrize("check", [_check_axis, _check_plane, _check_rotation, _check_matrix])
+def test_p7b_julia_generic_c(check):
+    for c in _generic_cs(21):
+        assert np.all(c != 0)
+        assert check(_oracle_julia, c), (check.__name__, c)
+
+
+def test_p7b_julia_generic_c_checks_reject_planted_mistakes():
+    """Each plausible way for c to enter the map wrongly fails at least one
+    of the checks (the mistakes are planted by feeding the oracle a
+    transformed c, on the CPU)."""
+    mutants = {
+        "c1 negated": lambda c: np.array([c[0], -c[1], c[2], c[3]]),
+        "c2 negated": lambda c: np.array([c[0], c[1], -c[2], c[3]]),
+        "c0 negated": lambda c: np.array([-c[0], c[1], c[2], c[3]]),
+        "c1, c2 swapped": lambda c: np.array([c[0], c[2], c[1], c[3]]),
+        "c1, c3 swapped": lambda c: np.array([c[0], c[3], c[2], c[1]]),
+        "c3 dropped": lambda c: np.array([c[0], c[1], c[2], 0.0]),
+        "c0, c1 swapped": lambda c: np.array([c[1], c[0], c[2], c[3]]),
+    }
+    checks = [_check_axis, _check_plane, _check_rotation, _check_matrix]
+    for name, f in mutants.items():
+        wrong = lambda p, c, f=f: _oracle_julia(p, f(np.asarray(c, np.float64)))
+        caught = [chk.__name__ for chk in checks if not all(chk(wrong, c) for c in _generic_cs(21))]
+        assert caught, f"planted mistake '{name}' passes every generic-c check"
+
+
 # ---------------------------------------------------------------- P8/P9 Mandelbulb
 
 def test_p8_mandelbulb_axis_is_real_recurrence():
