@@ -69,36 +69,36 @@ def ray_breakdown(counts):
                 bounce_shadow=int(counts[31]))
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle on a seeded pixel sample of the same frame, on the host cores."""
+def cpu_baseline():
+    """The FP64 oracle over the full 1080p teaser frame on the host cores.
+
+    P worker processes, P = the cores this process may run on, at most 16
+    (one GPU's share of the host cores).  The frame is split into 4P equal pixel chunks; the one-core rate is
+    one more chunk of the same size traced in this process (the same fixed
+    set-up cost per chunk as in the pool)."""
     import multiprocessing as mp
     import workloads as W
-    wl = W.c2()
-    req = wl.requests[0]
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    # calibrate on a small sample, then size the sample for ~target_s of wall time
-    pix0 = W.pixel_sample(1920, 1080, 800, seed=101)
-    t0 = time.perf_counter()
-    _oracle_chunk(pix0)
-    dt0 = time.perf_counter() - t0
-    rate = pix0.size / max(dt0, 1e-3)
-    # one core: a fresh sample sized for about 2 s in this process
-    pix1 = W.pixel_sample(1920, 1080, int(max(500, rate * 2.0)), seed=103)
-    t0 = time.perf_counter()
-    r1 = _oracle_chunk(pix1)
-    one_core = sum(r1["rays"].values()) / (time.perf_counter() - t0) / 1e6
-    n = int(min(1920 * 1080, max(2000, rate * target_s * cores * 0.8)))
-    pix = W.pixel_sample(1920, 1080, n, seed=102)
+    affinity = len(os.sched_getaffinity(0))
+    cores = max(1, min(16, affinity))
+    pix = np.arange(1920 * 1080, dtype=np.int64)
     chunks = np.array_split(pix, cores * 4)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         res = pool.map(_oracle_chunk, chunks)
     wall = time.perf_counter() - t0
     rays = sum(sum(r["rays"].values()) for r in res)
+    # one core: a chunk of the pool's size from a different part of the frame
+    one = W.pixel_sample(1920, 1080, chunks[0].size, seed=103)
+    t0 = time.perf_counter()
+    r1 = _oracle_chunk(one)
+    one_core = sum(r1["rays"].values()) / (time.perf_counter() - t0) / 1e6
     return {"value": rays / wall / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} seeded pixels of the 1920x1080 teaser frame (all their rays), "
-                      f"FP64 NumPy oracle in {cores} processes, {wall:.1f} s wall",
-            "one_core_value": round(one_core, 4), "cpu_model": _cpu_model()}
+            "sample": f"the full 1920x1080 teaser frame ({rays} rays: primary, shadow, bounce, "
+                      f"bounce-shadow), FP64 NumPy oracle in {cores} processes over {len(chunks)} "
+                      f"chunks of {chunks[0].size} pixels, {wall:.1f} s wall",
+            "one_core_value": round(one_core, 4),
+            "one_core_sample": f"{one.size} seeded pixels of the same frame in one process",
+            "affinity_cores": affinity, "cpu_model": _cpu_model()}
 
 
 def _cpu_model():

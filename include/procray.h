@@ -138,11 +138,17 @@ typedef struct pr_server pr_server;
 
 /* ---------------------------------------------------------------- scenes */
 
+/* Bound on the magnitude of every sample colour, per channel. */
+#define PR_MAX_COLOUR 16777216.0f   /* 2^24 */
+
 /* Copies all host arrays, validates them (known type; finite AABB with
  * lo <= hi; finite transform with |det A| > 1e-12; parameters in range:
  * radii > 0, 1 <= n_iter <= 64, bailout > 0, Mandelbulb power == 8 (else
  * PR_ERR_UNSUPPORTED); geometry and material indices in bounds; 1 <= n_inst
- * <= 16384, so that BVH stack entries fit 16 bits) and precomputes
+ * <= 16384, so that BVH stack entries fit 16 bits; colours bounded:
+ * |background| <= PR_MAX_COLOUR and |albedo| (|ambient| + |light_rgb|) <=
+ * PR_MAX_COLOUR per channel and material -- any sign is allowed -- so that
+ * every built-in sample colour stays within PR_MAX_COLOUR) and precomputes
  * per-instance records (A^-1, smallest singular value of A, local AABB,
  * parameters, material) on the host.  Touches no
  * device.  The scene is owned by the caller until pr_scene_destroy. */
@@ -233,7 +239,8 @@ pr_status pr_build_estimators(void);
  *          const float* k,                 the geometry's params[0..6]
  *          float* rgb)                     out: the hit's colour
  * It must depend on its arguments only: it is evaluated for lit = 0 and
- * lit = 1 before the shadow ray returns.  One per type; registering again
+ * lit = 1 before the shadow ray returns.  Each output channel is clamped to
+ * [-PR_MAX_COLOUR, PR_MAX_COLOUR] (a NaN stays NaN).  One per type; registering again
  * replaces the body.  Built with the estimators (pr_build_estimators or the
  * first render that needs them), with the same errors.  PR_ERR_INVALID_ARG
  * for a type that is not a registered user type or a body that is empty or
@@ -256,8 +263,10 @@ pr_status pr_register_closest_hit(uint32_t type, const char* body);
  * stream has finished.  1 <= width, height <= 16384.
  * With spp > 1 every sample is its own job; the library keeps 28 bytes per
  * pixel of scratch per in-flight launch (grown on demand, kept for reuse) for
- * exact fixed-point colour sums and per-pixel sample counters, so results do
- * not depend on the order in which samples finish.
+ * exact signed fixed-point colour sums (32.32 bits; sample colours are within
+ * PR_MAX_COLOUR) and per-pixel sample counters, so results do not depend on
+ * the order in which samples finish; a channel that is NaN in any sample is
+ * NaN in the mean.
  * PR_ERR_OUT_OF_MEMORY if that scratch cannot be allocated. */
 pr_status pr_render(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
                     uint32_t width, uint32_t height,

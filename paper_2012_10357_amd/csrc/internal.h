@@ -15,6 +15,10 @@ namespace pr {
 constexpr int kStackDepth = 32;       // BVH traversal stack entries per lane
 constexpr int kWave = 64;             // CDNA wavefront width
 constexpr int kBlock = 256;           // threads per workgroup (4 waves)
+// Bound on the magnitude of a sample colour: scene constants that could
+// exceed it are rejected by pr_scene_create and user closest-hit outputs are
+// clamped to it, so 32.32 fixed-point sums of up to 64 samples fit 63 bits.
+constexpr float kMaxColour = PR_MAX_COLOUR;   // 2^24
 
 // Type tag of a triangle leaf item (not a procedural type).
 constexpr uint32_t kTriangle = PR_NUM_TYPES;

@@ -448,6 +448,21 @@ pr_status pr_scene_create(const pr_geometry* geoms, uint32_t n_geom, const pr_in
           mats[m].reflectivity < 0.f || mats[m].reflectivity > 1.f)
         return set_error(PR_ERR_INVALID_ARG, "material %u: albedo finite and 0 <= rho <= 1 required", m);
     }
+    // Every built-in colour is albedo * (ambient + V lambert light_rgb) with
+    // V lambert in [0, 1], the background, or a convex blend of these, so
+    // bounding these terms bounds every sample colour (multi-sample means are
+    // exact fixed-point sums that need the bound).
+    for (int c = 0; c < 3; ++c)
+      if (!(std::fabs((double)consts->background[c]) <= (double)kMaxColour))
+        return set_error(PR_ERR_INVALID_ARG, "background colour beyond +-2^24");
+    for (uint32_t m = 0; m < n_mat; ++m)
+      for (int c = 0; c < 3; ++c) {
+        const double bound = std::fabs((double)mats[m].albedo[c]) *
+                             (std::fabs((double)consts->ambient) + std::fabs((double)consts->light_rgb[c]));
+        if (!(bound <= (double)kMaxColour))
+          return set_error(PR_ERR_INVALID_ARG,
+                           "material %u: |albedo| (|ambient| + |light_rgb|) beyond 2^24 in channel %d", m, c);
+      }
     auto* s = new pr_scene();
     s->host_insts.resize(n_inst);
     s->host_shade.resize(4 * (size_t)n_inst);

@@ -308,12 +308,18 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
 
   // A job is one sample.  With several samples per pixel the samples of a
   // pixel run as separate jobs on any lanes of any workgroup.  Each adds its
-  // colour, in 32.32 fixed point, to the pixel's 64-bit accumulators with
-  // device-scope atomics (integer sums are exact, so the mean does not depend
-  // on the order the samples finish in), waits until those adds are
-  // performed, then bumps the pixel's sample counter.  The sample that
-  // completes the count takes the sums with atomic exchanges, which also
-  // clear the accumulators for the next launch, and writes the mean.
+  // colour, in signed 32.32 fixed point, to the pixel's 64-bit accumulators
+  // with device-scope atomics (two's-complement integer sums are exact, so the
+  // mean does not depend on the order the samples finish in), waits until
+  // those adds are performed, then bumps the pixel's sample counter.  The
+  // sample that completes the count takes the sums with atomic exchanges,
+  // which also clear the accumulators for the next launch, and writes the
+  // mean.  Colours are bounded by kMaxColour = 2^24 in magnitude (the scene
+  // constants are validated on the host and user closest-hit outputs are
+  // clamped), so each term is below 2^56 and 64 of them stay below 2^62.  A
+  // NaN channel adds nothing and is counted instead, in a 7-bit field of the
+  // counter word per channel (bits 0-6 count samples); the mean of a channel
+  // that saw a NaN is NaN, as in floating point.
   auto finish_sample = [&](float cr, float cg, float cb) __attribute__((always_inline)) {
     const size_t pix = (size_t)py * R->width + px;
     float* o = R->out_rgb + pix * 3;
@@ -322,21 +328,27 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       o[1] = cg;
       o[2] = cb;
     } else {
-      // colours are >= 0 and far below 2^31, so 64-bit sums never overflow
       constexpr float kFix = 4294967296.0f;  // 2^32
       unsigned long long* acc = R->sample_acc + pix * 3;
-      atomicAdd(acc + 0, (unsigned long long)__float2ull_rn(cr * kFix));
-      atomicAdd(acc + 1, (unsigned long long)__float2ull_rn(cg * kFix));
-      atomicAdd(acc + 2, (unsigned long long)__float2ull_rn(cb * kFix));
+      const bool nr = cr != cr, ng = cg != cg, nb = cb != cb;
+      atomicAdd(acc + 0, (unsigned long long)__float2ll_rn(nr ? 0.f : cr * kFix));
+      atomicAdd(acc + 1, (unsigned long long)__float2ll_rn(ng ? 0.f : cg * kFix));
+      atomicAdd(acc + 2, (unsigned long long)__float2ll_rn(nb ? 0.f : cb * kFix));
       // vmcnt also counts stores and atomics without return: wait until the
       // three adds are acknowledged before the counter can reach its total
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      const uint32_t before = atomicAdd(&R->sample_cnt[pix], 1u);
-      if (before == spp - 1) {
+      const uint32_t add = 1u + (nr ? 1u << 7 : 0u) + (ng ? 1u << 14 : 0u) + (nb ? 1u << 21 : 0u);
+      const uint32_t before = atomicAdd(&R->sample_cnt[pix], add);
+      if ((before & 127u) == spp - 1) {
+        const uint32_t nan = before + add;
         const double scale = 1.0 / (4294967296.0 * (double)spp);
-        o[0] = (float)((double)atomicExch(acc + 0, 0ull) * scale);
-        o[1] = (float)((double)atomicExch(acc + 1, 0ull) * scale);
-        o[2] = (float)((double)atomicExch(acc + 2, 0ull) * scale);
+        const double qnan = __builtin_nan("");
+        const double sr = (double)(long long)atomicExch(acc + 0, 0ull) * scale;
+        const double sg = (double)(long long)atomicExch(acc + 1, 0ull) * scale;
+        const double sb = (double)(long long)atomicExch(acc + 2, 0ull) * scale;
+        o[0] = (float)((nan >> 7) & 127u ? qnan : sr);
+        o[1] = (float)((nan >> 14) & 127u ? qnan : sg);
+        o[2] = (float)((nan >> 21) & 127u ? qnan : sb);
         atomicExch(&R->sample_cnt[pix], 0u);
       }
     }
@@ -604,8 +616,10 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         user_shade(I.type, hx, hy, hz, nx, ny, nz, -ray.dx, -ray.dy, -ray.dz, lux, luy, luz, 1.f, mat,
                    sc->ambient, sc->light_rgb, I.prm, c1);
         sh_user = true;
-        sh_ar = c0[0]; sh_ag = c0[1]; sh_ab = c0[2];
-        sh_lr = c1[0]; sh_lg = c1[1]; sh_lb = c1[2];
+        // outputs are clamped to the colour bound (NaN stays NaN)
+        auto clampc = [](float v) { return v != v ? v : fminf(fmaxf(v, -kMaxColour), kMaxColour); };
+        sh_ar = clampc(c0[0]); sh_ag = clampc(c0[1]); sh_ab = clampc(c0[2]);
+        sh_lr = clampc(c1[0]); sh_lg = clampc(c1[1]); sh_lb = clampc(c1[2]);
       }
     }
     const bool may_hand_off = !sh_user;

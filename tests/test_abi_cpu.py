@@ -73,6 +73,25 @@ def test_invalid_scenes_rejected_before_device(P):
     P.Scene(cut, build=False).close()
 
 
+def test_colour_bound_validated(P):
+    """Sample colours must stay within 2^24 in magnitude (multi-sample means
+    are exact signed 32.32 fixed-point sums): background and
+    |albedo| (|ambient| + |light_rgb|) beyond it are rejected; signed values
+    within it are accepted."""
+    ok = W.c2_scene(); ok.mat_albedo = np.array([[-0.5, 0.2, 3.0], [0.1, -2.0, 0.0], [1, 1, 1]], np.float32)
+    ok.background = np.array([-1.0, 0.5, 2.0 ** 24], np.float32)
+    P.Scene(ok, build=False).close()
+    bad = W.c2_scene(); bad.background = np.array([0, 0, -2.0 ** 24 * 1.001], np.float32)
+    with pytest.raises(P.ProcrayError, match="background"):
+        P.Scene(bad, build=False)
+    bad = W.c2_scene(); bad.mat_albedo = bad.mat_albedo.copy(); bad.mat_albedo[1, 2] = -1.6e7
+    with pytest.raises(P.ProcrayError, match="albedo"):
+        P.Scene(bad, build=False)   # 1.6e7 * (0.1 + 1) > 2^24
+    bad = W.c2_scene(); bad.light_rgb = np.array([1, 1e20, 1], np.float32)
+    with pytest.raises(P.ProcrayError, match="albedo"):
+        P.Scene(bad, build=False)
+
+
 def test_render_argument_errors_before_device(P):
     sc = P.Scene(W.c1_scene(), build=False)
     cam = W.camera((0, 1, -4))

@@ -30,13 +30,16 @@ def _register(P):
         P.register_closest_hit(_types["cyl_ch"], U.STRIPED_CH_BODY)
         P.register_closest_hit(_types["cyl_lam"], U.LAMBERT_CH_BODY)
         # the benchmark's user hit group: the teaser's pac-man and Lambert shading restated
+        _types["cyl_signed"] = P.register_estimator("gpu_test_cylinder_signed", U.CYLINDER_BODY)
+        P.register_closest_hit(_types["cyl_signed"], U.SIGNED_CH_BODY)
         _types["pac"] = P.register_estimator("gpu_test_user_pacman", bench.F3_PACMAN_BODY)
         P.register_closest_hit(_types["pac"], bench.F3_LAMBERT_BODY)
         D.register_estimator(_types["pac"],
                              lambda p, k: D.de_pacman(p, k[:, 0], np.arctan2(k[:, 2], k[:, 1])))
         D.register_closest_hit(_types["pac"], U.lambert_ch_np)
-        for k in ("cyl", "cyl_ch", "cyl_lam"):
+        for k in ("cyl", "cyl_ch", "cyl_lam", "cyl_signed"):
             D.register_estimator(_types[k], U.cylinder_np)
+        D.register_closest_hit(_types["cyl_signed"], U.signed_ch_np)
         D.register_estimator(_types["oct"], U.octahedron_np)
         D.register_closest_hit(_types["cyl_ch"], U.striped_ch_np)
         D.register_closest_hit(_types["cyl_lam"], U.lambert_ch_np)
@@ -185,3 +188,57 @@ def test_user_pacmen_teaser_against_oracle_and_builtin():
     gb = gpu_render(P, P.Scene(W.c2_scene()), cam, opts)
     assert np.mean(g[2] == gb[2]) >= 0.999
     assert set(np.unique(g[2])) >= {0, 1, 2, 3}
+
+
+def _signed_scene(types):
+    """Cylinders shaded by the signed closest-hit function, a sphere of
+    negative albedo in two channels and a plane, nothing reflective."""
+    b = W._SceneBuilder()
+    m_c = b.material((0.2, 0.7, 0.4), 0.0)
+    m_s = b.material((-0.6, 0.6, -0.9), 0.0)
+    m_g = b.material((0.75, -0.5, 0.75), 0.0)
+    aabb, prm = U.cylinder_geom(0.5, 0.9)
+    g_c = b.geometry((types["cyl_signed"], aabb, prm))
+    b.instance(g_c, m_c, W.xform(W._rot_x(0.4), 1.0, (-1.4, 0.0, 0.3)))
+    b.instance(g_c, m_c, W.xform(W._rot_y(0.6) @ W._rot_x(1.2), 0.7, (1.6, -0.3, -0.4)))
+    b.instance(b.geometry(W.geom_sphere(0.6)), m_s, W.xform(np.eye(3), 1.0, (0.2, -0.4, -1.2)))
+    b.mesh(W.QUAD_VERTICES, W.QUAD_INDICES, [(m_g, W.xform(np.eye(3), 8.0, (0.0, -1.0, 0.0)))])
+    return b.build(light_pos=(2, 4, -3), background=(-0.25, 0.0, 0.5))
+
+
+@pytest.mark.parametrize("spp", [1, 4])
+def test_signed_and_clamped_colours_against_oracle(spp):
+    """Signed colours (negative albedo and background, a user closest-hit
+    returning a signed normal component), a channel beyond the colour bound
+    (clamped to 2^24) and NaN channels, averaged over 4 jittered samples by the
+    fixed-point accumulators: parity with the oracle, the same NaN pixels, and
+    the clamped channel exactly 2^24 where every sample hits a cylinder."""
+    P = require_gpu()
+    types = _register(P)
+    scene = _signed_scene(types)
+    cam = W.camera((0.0, 1.2, -5.0))
+    opts = W.RenderOpts(128, 96, spp=spp, jitter=1, seed=77, max_steps=256, shadows=1, bounces=0)
+    g = gpu_render(P, P.Scene(scene), cam, opts)
+    orc = T.render(scene, cam, opts)
+    g_rgb = g[0].reshape(-1, 3).astype(np.float64)
+    keep = orc["excl"] == 0
+    nan_g, nan_o = np.isnan(g_rgb), np.isnan(orc["rgb"])
+    assert nan_o[:, 1].sum() > 100 and not nan_o[:, [0, 2]].any()
+    assert np.mean((nan_g == nan_o).all(axis=1)[keep]) >= 0.999
+    assert (g_rgb < 0).any() and (orc["rgb"] < 0).any()
+    both = ~(nan_g | nan_o)
+    g_rgb = np.where(both, g_rgb, 0.0)
+    o_rgb = np.where(both, orc["rgb"], 0.0)
+    # the clamped channel: exactly 2^24 where every sample hits a cylinder;
+    # a mean of mixed samples (up to 2^24) is compared at float32 resolution
+    full = o_rgb[:, 2] == 2.0 ** 24
+    assert full.sum() > 300
+    assert np.all(g_rgb[full & keep, 2] == 2.0 ** 24)
+    agree = keep & ((g[2].reshape(-1) >= 0) == (orc["inst"] >= 0))
+    err2 = np.abs(g_rgb[:, 2] - o_rgb[:, 2])
+    assert np.mean((err2 <= 1e-3 + np.abs(o_rgb[:, 2]) * 2.0 ** -23)[agree]) >= 0.999
+    g_rgb[:, 2] = 0.0
+    o_rgb[:, 2] = 0.0
+    rep = parity.compare(g_rgb, g[1], g[2], dict(orc, rgb=o_rgb), f"signed colours spp={spp}")
+    print(parity.fmt(rep), flush=True)
+    assert rep["pass"], parity.fmt(rep)

@@ -79,3 +79,23 @@ def striped_ch_np(p, n, v, l, lit, albedo, ambient, light_rgb, k):
     sp = np.where(hl > 0.0, np.maximum(0.0, np.sum(n * h, axis=1) / np.where(hl > 0.0, hl, 1.0)), 0.0)
     return (stripe[:, None] * albedo * (ambient + (lit * lam)[:, None] * light_rgb[None, :])
             + (lit * 0.5 * sp ** 16)[:, None] * light_rgb[None, :] + 0.1 * k[:, 0:1])
+
+
+# Signed, out-of-range and NaN colours: a signed normal component, a
+# negated Lambert term that is NaN above world height 0.2, and a channel far
+# beyond the library's colour bound (clamped to 2^24 on both sides).
+SIGNED_CH_BODY = """
+  const float lam = fmaxf(0.f, nx * lx + ny * ly + nz * lz);
+  rgb[0] = nx - 0.25f * ny;
+  rgb[1] = py > 0.2f ? __builtin_nanf("") : -albedo[1] * (ambient + lit * lam * light_rgb[1]);
+  rgb[2] = 1e30f;
+"""
+
+
+def signed_ch_np(p, n, v, l, lit, albedo, ambient, light_rgb, k):
+    lam = np.maximum(0.0, np.sum(n * l, axis=1))
+    out = np.empty((p.shape[0], 3))
+    out[:, 0] = n[:, 0] - 0.25 * n[:, 1]
+    out[:, 1] = np.where(p[:, 1] > 0.2, np.nan, -albedo[:, 1] * (ambient + lit * lam * light_rgb[1]))
+    out[:, 2] = 1e30
+    return out
