@@ -68,6 +68,8 @@ E4_MAX_DN = 1e-3
 _E4_DIRS = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float64) / np.sqrt(3.0)
 
 M32 = 0xFFFFFFFF
+# magnitude bound of a user closest-hit colour (outputs beyond it are clamped)
+USER_COLOUR_BOUND = 2.0 ** 24
 
 
 def lowbias32(x):
@@ -654,15 +656,18 @@ def _shade_hits(prep, opts, o, d, tr, counts, kind_shadow, extra_shift=None):
     ell = _normalize(prep.light[None, :] - p)
     lam = np.maximum(0.0, np.sum(n * ell, axis=1))
     c = prep.albedo[inst] * (prep.ambient + (V * lam)[:, None] * prep.light_rgb[None, :])
-    # hits on a user type with a closest-hit function take their colour from it
+    # hits on a user type with a closest-hit function take their colour from
+    # it, clamped to the library's colour bound of 2^24 in magnitude (a NaN
+    # stays NaN): the boundary states this clamp for user shading outputs
     if D.CLOSEST_HIT and proc.any():
         gt = np.full(hidx.size, -1, np.int64)
         gt[proc] = prep.gtype[inst[proc]]
         for ty, fn in D.CLOSEST_HIT.items():
             sel = gt == ty
             if sel.any():
-                c[sel] = np.asarray(fn(p[sel], n[sel], -d[hidx[sel]], ell[sel], V[sel], prep.albedo[inst[sel]],
-                                       float(prep.ambient), prep.light_rgb, prep.prm[inst[sel]]), np.float64)
+                cu = np.asarray(fn(p[sel], n[sel], -d[hidx[sel]], ell[sel], V[sel], prep.albedo[inst[sel]],
+                                   float(prep.ambient), prep.light_rgb, prep.prm[inst[sel]]), np.float64)
+                c[sel] = np.clip(cu, -USER_COLOUR_BOUND, USER_COLOUR_BOUND)
     col[hidx] = c
     nrm[hidx] = n
     pw[hidx] = p
