@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 5
+#define PR_ABI_VERSION 6
 
 typedef enum {
   PR_OK = 0,
@@ -271,6 +271,28 @@ pr_status pr_register_closest_hit(uint32_t type, const char* body);
 pr_status pr_render(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
                     uint32_t width, uint32_t height,
                     float* out_rgb, float* out_t, int32_t* out_inst, void* hip_stream);
+
+/* pr_render for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc): the
+ * same frame and the same results, with no allocation of any kind on the
+ * device or in pinned host memory.  The launch record and, for spp > 1, the
+ * per-pixel accumulators live in a fixed scratch array of
+ * PR_NOALLOC_SCRATCH_BYTES per device, held from the library's first use of
+ * the device until the process ends; the request reaches the device as a
+ * kernel argument.  Arguments and errors as for pr_render, and:
+ *  - spp > 1 needs 4096 + 28 * width * height bytes (rounded up) of the
+ *    scratch: at most about 2.39 million pixels (1920x1080 fits); larger
+ *    requests return PR_ERR_INVALID_ARG before any device work;
+ *  - scenes with user estimators return PR_ERR_UNSUPPORTED (their kernel is
+ *    built and loaded at run time);
+ *  - every call on a device shares that device's scratch: calls that may
+ *    overlap on one device (other streams, other threads) race and must be
+ *    serialised by the caller; the array keeps the last call's contents, and
+ *    each call clears what it needs at zero itself. */
+#define PR_NOALLOC_SCRATCH_BYTES (64u << 20)
+pr_status pr_render_noalloc(pr_scene* scene, const pr_camera* cam, const pr_render_opts* opts,
+                            uint32_t width, uint32_t height,
+                            float* out_rgb, float* out_t, int32_t* out_inst, void* hip_stream);
 
 /* Work counters of one frame, for flop accounting: the same render run by
  * an instrumented build of the kernel (never the timed one), synchronous.

@@ -32,7 +32,7 @@ EXPORTS = [
     "pr_server_create", "pr_server_create_simulated", "pr_server_add_scene", "pr_server_submit", "pr_server_wait",
     "pr_server_release", "pr_server_stats_get", "pr_server_destroy", "pr_last_error",
     "pr_abi_version", "pr_device_count", "pr_launch_shape", "pr_register_estimator", "pr_build_estimators",
-    "pr_register_closest_hit",
+    "pr_register_closest_hit", "pr_render_noalloc",
 ]
 
 
@@ -122,7 +122,7 @@ assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(Rend
 assert C.sizeof(BvhNode) == 32
 
 # The C ABI revision these ctypes layouts and signatures describe.
-PR_ABI_VERSION = 5
+PR_ABI_VERSION = 6
 
 _lib = None
 
@@ -146,6 +146,7 @@ def lib():
         "pr_scene_device_bytes": [P, C.POINTER(U64)],
         "pr_scene_destroy": [P],
         "pr_render": [P, P, P, U32, U32, P, P, P, P],
+        "pr_render_noalloc": [P, P, P, U32, U32, P, P, P, P],
         "pr_render_counts": [P, P, P, U32, U32, P, P],
         "pr_render_batch": [P, U32, P, P],
         "pr_autotune": [P, U32, P],
@@ -304,6 +305,16 @@ def render(scene: Scene, cam, opts, out_rgb, out_t=None, out_inst=None, stream=N
     c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order)
     _check(lib().pr_render(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), _ptr(out_t),
                            _ptr(out_inst), _stream_ptr(stream)))
+
+
+def render_noalloc(scene: Scene, cam, opts, out_rgb, out_t=None, out_inst=None, stream=None,
+                   tile=(0, 0), step_budget=0, natural_order=False):
+    """pr_render_noalloc: pr_render with no device allocation (fixed per-device
+    scratch; overlapping calls on one device race)."""
+    H, W = out_rgb.shape[0], out_rgb.shape[1]
+    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order)
+    _check(lib().pr_render_noalloc(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), _ptr(out_t),
+                                   _ptr(out_inst), _stream_ptr(stream)))
 
 
 def render_counts(scene: Scene, cam, opts, out_rgb, tile=(0, 0), step_budget=0) -> np.ndarray:

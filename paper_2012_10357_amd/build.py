@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprocray.so")
 
-SOURCES = ["trace.hip", "scene.cpp", "render.cpp", "server.cpp", "user_de.cpp"]
+SOURCES = ["trace.hip", "noalloc.hip", "scene.cpp", "render.cpp", "server.cpp", "user_de.cpp"]
 
 # Kernel sources the library carries as text, to rebuild the kernel with
 # user-registered estimators at run time.

@@ -504,6 +504,9 @@ pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes,
   return PR_OK;
 }
 
+// Persistent grid of the built-in kernel for a launch of total_jobs jobs.
+int persistent_grid(uint32_t total_jobs) { return grid_for(total_jobs); }
+
 int budget_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_budget) {
   if (o && o->step_budget) return (int)o->step_budget;
   if (override_budget) return (int)override_budget;

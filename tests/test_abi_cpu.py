@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == P.PR_ABI_VERSION == 5
+    assert P.abi_version() == P.PR_ABI_VERSION == 6
     assert P.device_count() >= 0
 
 
@@ -123,6 +123,17 @@ def test_render_argument_errors_before_device(P):
     # host-only build: not uploaded, so rendering is refused before any device call
     with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
         P.render(sc, cam, o, fake)
+    # the allocation-free entry point: the same refusal, and requests whose
+    # multi-sample accumulators would not fit its fixed scratch are rejected
+    # before anything else (1920x1080 at 4 spp fits, 2048x2048 at 2 does not)
+    with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
+        P.render_noalloc(sc, cam, W.RenderOpts(1920, 1080, spp=4, max_steps=128),
+                         type("T", (), {"shape": (1080, 1920, 3), "data_ptr": lambda self: 0})())
+    huge = type("T", (), {"shape": (2048, 2048, 3), "data_ptr": lambda self: 0})()
+    with pytest.raises(P.ProcrayError, match="scratch"):
+        P.render_noalloc(sc, cam, W.RenderOpts(2048, 2048, spp=2, max_steps=128), huge)
+    with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
+        P.render_noalloc(sc, cam, W.RenderOpts(2048, 2048, spp=1, max_steps=128), huge)
     # batches: empty, more than 4096 requests, a tile that is not 64 pixels,
     # and a request whose scene is not on the device (named by its index)
     one = P.make_requests([(sc, cam, o, fake, None, None, 0)])
