@@ -35,7 +35,9 @@ Besides colour, distance and instance index the oracle reports, per pixel,
 whether any traced ray passed within 1e-3 of a surface without stopping
 (E1), ran out of march steps (E2), stopped with a value in [0.98 eps, eps)
 (E3), or hit where the normal itself is ill-conditioned -- it turns by more
-than 5e-4 when the hit point moves by four float32 ulps of t (E4) -- the
+than 1e-3 when the hit point moves by 1e-7 t, about the float32 error of a
+hit point, along any of four fixed directions; for a bounce hit also by the
+displacement its direction inherits from the primary normal (E4) -- the
 places where float32 and float64 may legitimately differ -- and per-type
 counts of estimator evaluations and fractal iterations in canonical
 front-to-back order (for work accounting).
