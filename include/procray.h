@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 6
+#define PR_ABI_VERSION 7
 
 typedef enum {
   PR_OK = 0,
@@ -112,14 +112,24 @@ typedef struct { float eye[3], target[3], up[3], vfov_deg; } pr_camera;
  *                 screen rectangle covered by the iterative fractals
  *                 (Julia, Mandelbulb) of scenes with at most 256 instances,
  *                 so their long sphere-tracing chains start early
- * The four scheduling fields never change results. */
+ *  compact_pct    regrouping of live rays: 1..100 = a workgroup pools its
+ *                 lanes' sphere-trace queries, sorted by primitive type, and
+ *                 re-issues them as full waves whenever fewer than
+ *                 compact_pct % of its lanes march or one of its waves
+ *                 marches more than one primitive type; PR_COMPACT_NEVER =
+ *                 every wave marches its own lanes; 0 = the choice stored for
+ *                 the scene's size class (pr_autotune), else the default
+ *  reserved       must be 0
+ * The five scheduling fields never change results.  72 bytes. */
 typedef struct {
   uint64_t seed;
   uint32_t spp, jitter, max_steps, shadows, bounces;
   float eps, tmin, tmax, shadow_offset, fd_h;
   uint32_t tile_w, tile_h, step_budget, flags;
+  uint32_t compact_pct, reserved;
 } pr_render_opts;
 #define PR_RENDER_NATURAL_ORDER 1u
+#define PR_COMPACT_NEVER 1000u
 
 /* BVH build options: SAH bins (4..256), maximum leaf size (1..8), traversal
  * and leaf costs; flags bit 0 (PR_BVH_HOST_ONLY) builds without uploading,
@@ -316,8 +326,9 @@ typedef struct {
 } pr_request;
 
 /* use_graph: 1 = replay a captured hipGraph of (request-table copy, queue
- * reset, persistent kernel); tile_w/tile_h/step_budget: 0 = autotuned. */
-typedef struct { uint32_t tile_w, tile_h, step_budget, use_graph; } pr_batch_opts;
+ * reset, persistent kernel); tile_w/tile_h/step_budget/compact_pct: 0 =
+ * autotuned (compact_pct as in pr_render_opts, for the whole launch). */
+typedef struct { uint32_t tile_w, tile_h, step_budget, use_graph, compact_pct; } pr_batch_opts;
 
 /* Renders n requests (possibly of different scenes, resolutions and sample
  * counts) in one persistent launch that pops tiles from a device queue
@@ -326,9 +337,10 @@ typedef struct { uint32_t tile_w, tile_h, step_budget, use_graph; } pr_batch_opt
 pr_status pr_render_batch(const pr_request* reqs, uint32_t n, const pr_batch_opts* opts,
                           void* hip_stream);
 
-/* Autotuner: times the candidate tile shapes and step budgets on the given
- * requests (synchronously, several launches each) and stores the best for
- * scenes of this size class; later calls with 0 fields use it.  best
+/* Autotuner: times the candidate tile shapes, step budgets and regrouping
+ * choices on the given requests (synchronously, several launches each) and
+ * stores the best for scenes of this size class; later calls with 0 fields
+ * use it.  best
  * (nullable) receives the choice.  The cache is saved to the JSON file named
  * by the PR_AUTOTUNE_CACHE environment variable when set. */
 pr_status pr_autotune(const pr_request* reqs, uint32_t n, pr_batch_opts* best);

@@ -75,7 +75,8 @@ class RenderOptsC(C.Structure):
                 ("max_steps", C.c_uint32), ("shadows", C.c_uint32), ("bounces", C.c_uint32),
                 ("eps", C.c_float), ("tmin", C.c_float), ("tmax", C.c_float),
                 ("shadow_offset", C.c_float), ("fd_h", C.c_float), ("tile_w", C.c_uint32),
-                ("tile_h", C.c_uint32), ("step_budget", C.c_uint32), ("flags", C.c_uint32)]
+                ("tile_h", C.c_uint32), ("step_budget", C.c_uint32), ("flags", C.c_uint32),
+                ("compact_pct", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class BvhOpts(C.Structure):
@@ -96,7 +97,7 @@ class RequestC(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("tile_w", C.c_uint32), ("tile_h", C.c_uint32), ("step_budget", C.c_uint32),
-                ("use_graph", C.c_uint32)]
+                ("use_graph", C.c_uint32), ("compact_pct", C.c_uint32)]
 
 
 class ServerOpts(C.Structure):
@@ -118,11 +119,11 @@ class ServerStats(C.Structure):
 
 
 assert C.sizeof(Geometry) == 76 and C.sizeof(Instance) == 56 and C.sizeof(Material) == 16
-assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(RenderOptsC) == 64
+assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(RenderOptsC) == 72
 assert C.sizeof(BvhNode) == 32
 
 # The C ABI revision these ctypes layouts and signatures describe.
-PR_ABI_VERSION = 6
+PR_ABI_VERSION = 7
 
 _lib = None
 
@@ -196,12 +197,14 @@ def camera_c(cam) -> CameraC:
 
 
 PR_RENDER_NATURAL_ORDER = 1
+PR_COMPACT_NEVER = 1000
 
 
-def opts_c(o, tile=(0, 0), step_budget=0, natural_order=False) -> RenderOptsC:
+def opts_c(o, tile=(0, 0), step_budget=0, natural_order=False, compact=0) -> RenderOptsC:
+    """compact: 0 = tuned choice, 1..100 = regrouping threshold, PR_COMPACT_NEVER = none."""
     return RenderOptsC(int(o.seed) & 0xFFFFFFFFFFFFFFFF, o.spp, o.jitter, o.max_steps, o.shadows,
                        o.bounces, o.eps, o.tmin, o.tmax, o.shadow_offset, o.fd_h, tile[0], tile[1],
-                       step_budget, PR_RENDER_NATURAL_ORDER if natural_order else 0)
+                       step_budget, PR_RENDER_NATURAL_ORDER if natural_order else 0, compact, 0)
 
 
 class Scene:
@@ -299,27 +302,27 @@ def _stream_ptr(stream):
 
 
 def render(scene: Scene, cam, opts, out_rgb, out_t=None, out_inst=None, stream=None,
-           tile=(0, 0), step_budget=0, natural_order=False):
+           tile=(0, 0), step_budget=0, natural_order=False, compact=0):
     """pr_render into caller-owned torch CUDA tensors (H, W, 3) / (H, W) / (H, W)."""
     H, W = out_rgb.shape[0], out_rgb.shape[1]
-    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order)
+    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order, compact)
     _check(lib().pr_render(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), _ptr(out_t),
                            _ptr(out_inst), _stream_ptr(stream)))
 
 
 def render_noalloc(scene: Scene, cam, opts, out_rgb, out_t=None, out_inst=None, stream=None,
-                   tile=(0, 0), step_budget=0, natural_order=False):
+                   tile=(0, 0), step_budget=0, natural_order=False, compact=0):
     """pr_render_noalloc: pr_render with no device allocation (fixed per-device
     scratch; overlapping calls on one device race)."""
     H, W = out_rgb.shape[0], out_rgb.shape[1]
-    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order)
+    c, o = camera_c(cam), opts_c(opts, tile, step_budget, natural_order, compact)
     _check(lib().pr_render_noalloc(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), _ptr(out_t),
                                    _ptr(out_inst), _stream_ptr(stream)))
 
 
-def render_counts(scene: Scene, cam, opts, out_rgb, tile=(0, 0), step_budget=0) -> np.ndarray:
+def render_counts(scene: Scene, cam, opts, out_rgb, tile=(0, 0), step_budget=0, compact=0) -> np.ndarray:
     H, W = out_rgb.shape[0], out_rgb.shape[1]
-    c, o = camera_c(cam), opts_c(opts, tile, step_budget)
+    c, o = camera_c(cam), opts_c(opts, tile, step_budget, compact=compact)
     counts = (C.c_uint64 * PR_NUM_COUNTS)()
     _check(lib().pr_render_counts(scene.handle, C.byref(c), C.byref(o), W, H, _ptr(out_rgb), counts))
     return np.array(counts[:], np.uint64)
@@ -341,8 +344,8 @@ def make_requests(items) -> "C.Array":
     return arr
 
 
-def render_batch(reqs, tile=(0, 0), step_budget=0, use_graph=False, stream=None):
-    bo = BatchOpts(tile[0], tile[1], step_budget, 1 if use_graph else 0)
+def render_batch(reqs, tile=(0, 0), step_budget=0, use_graph=False, stream=None, compact=0):
+    bo = BatchOpts(tile[0], tile[1], step_budget, 1 if use_graph else 0, compact)
     _check(lib().pr_render_batch(reqs, len(reqs), C.byref(bo), _stream_ptr(stream)))
 
 

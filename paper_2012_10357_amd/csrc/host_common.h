@@ -39,6 +39,7 @@ struct LaunchCtx {
   int graph_blocks = 0, graph_budget = 0;
   hipStream_t graph_stream = nullptr;
   const void* graph_kernel = nullptr;   // the kernel the graph launches (nullptr: built-in)
+  int graph_compact = 0;                // regrouping threshold the graph's kernel runs with
 };
 
 LaunchCtx* acquire_ctx(uint32_t n_req);

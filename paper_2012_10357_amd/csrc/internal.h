@@ -112,13 +112,17 @@ static_assert(sizeof(ReqDev) == 192, "request record");
 // Work queue of one launch.  When every
 // request of the launch renders the same scene, that scene's top BVH nodes,
 // first instance records and constants are staged in LDS by every workgroup.
+// compact_pct > 0 selects the regrouping kernel: a workgroup pools its lanes'
+// march queries, sorted by primitive type, whenever fewer than compact_pct %
+// of its lanes march or one of its waves marches more than one type.
 struct alignas(16) QueueDev {
   uint32_t next_job;       // popped with atomicAdd
   uint32_t total_jobs;
   uint32_t n_req;
   uint32_t n_stage_nodes;  // 0 = no staging
   uint32_t n_stage_insts;
-  uint32_t pad0, pad1, pad2;
+  uint32_t compact_pct;    // 0: waves march their own lanes; 1..100: regroup threshold
+  uint32_t pad1, pad2;
   const NodeDev* stage_nodes;     // global source of the staged scene
   const InstDev* stage_insts;
   const SceneConstsDev* stage_consts;
@@ -136,6 +140,7 @@ constexpr int kNumCounts = PR_NUM_COUNTS;
 struct LaunchCfg {
   int step_budget;   // DE evaluations between refill checks
   int grid_blocks;   // persistent grid size
+  int compact_pct;   // 0 = no regrouping (also written to the queue header)
 };
 
 }  // namespace pr

@@ -22,6 +22,7 @@ pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes,
                       float* t, int32_t* inst, uint32_t tile_w_override, uint32_t& total_jobs,
                       bool check_ptrs);
 int budget_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_budget);
+int compact_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_pct);
 int persistent_grid(uint32_t total_jobs);
 }  // namespace pr
 
@@ -117,10 +118,12 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
       r.sample_cnt = (uint32_t*)(base + kAccOffset + up256(px * 24));
       zero16 = (up256(px * 24) + up256(px * 4)) / 16;
     }
+    const int compact = compact_for(s, opts, 0);
     QueueDev q;
     std::memset(&q, 0, sizeof q);
     q.total_jobs = total;
     q.n_req = 1;
+    q.compact_pct = (uint32_t)compact;
     // one scene: every workgroup stages its top BVH levels, first instance
     // records and constants in LDS, as for pr_render
     q.n_stage_nodes = std::min<uint32_t>((uint32_t)s->dnodes.size(), kLdsNodes);
@@ -133,7 +136,7 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
     const uint32_t setup_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (zero16 + 255) / 256));
     hipLaunchKernelGGL(noalloc_setup, dim3(setup_blocks), dim3(256), 0, (hipStream_t)stream, q, r, base, zero16);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "noalloc_setup launch");
-    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total)};
+    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact};
     if (launch_trace((const ReqDev*)(base + sizeof(QueueDev)), (QueueDev*)base, total, 1, cfg, nullptr, stream) != 0)
       return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (s->last_use && (e = hipEventRecord(s->last_use, (hipStream_t)stream)) != hipSuccess)

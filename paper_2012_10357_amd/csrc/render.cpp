@@ -74,6 +74,7 @@ namespace {
 // steps delay the refills and priority updates that the longest pixels need).
 struct Tuned {
   uint32_t tile_w = 8, step_budget = 24;
+  uint32_t compact = 0;   // 0 = no regrouping, 1..100 = threshold
 };
 
 std::mutex g_tune_mu;
@@ -100,7 +101,7 @@ void load_tune_cache() {
   if (!path) return;
   std::ifstream f(path);
   if (!f) return;
-  // minimal format: {"key": [tile_w, step_budget], ...}
+  // minimal format: {"key": [tile_w, step_budget, compact_pct], ...}
   std::string all((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
   size_t p = 0;
   while ((p = all.find('"', p)) != std::string::npos) {
@@ -110,9 +111,11 @@ void load_tune_cache() {
     size_t lb = all.find('[', q), rb = all.find(']', q);
     if (lb == std::string::npos || rb == std::string::npos) break;
     Tuned t;
-    if (std::sscanf(all.c_str() + lb, "[%u , %u]", &t.tile_w, &t.step_budget) == 2 ||
-        std::sscanf(all.c_str() + lb, "[%u,%u]", &t.tile_w, &t.step_budget) == 2)
+    if (std::sscanf(all.c_str() + lb, "[%u , %u , %u]", &t.tile_w, &t.step_budget, &t.compact) >= 2 ||
+        std::sscanf(all.c_str() + lb, "[%u,%u,%u]", &t.tile_w, &t.step_budget, &t.compact) >= 2) {
+      if (t.compact > 100) t.compact = 0;
       g_tuned[key] = t;
+    }
     p = rb + 1;
   }
 }
@@ -125,7 +128,7 @@ void save_tune_cache() {
   bool first = true;
   for (auto& kv : g_tuned) {
     f << (first ? "" : ", ") << "\"" << kv.first << "\": [" << kv.second.tile_w << ", "
-      << kv.second.step_budget << "]";
+      << kv.second.step_budget << ", " << kv.second.compact << "]";
     first = false;
   }
   f << "}\n";
@@ -176,6 +179,9 @@ pr_status validate_opts(const pr_render_opts* o, uint32_t w, uint32_t h) {
     return set_error(PR_ERR_INVALID_ARG, "tile_w * tile_h must be 64");
   if (o->step_budget > 4096) return set_error(PR_ERR_INVALID_ARG, "step_budget must be <= 4096");
   if (o->flags & ~PR_RENDER_NATURAL_ORDER) return set_error(PR_ERR_INVALID_ARG, "unknown render flags");
+  if (o->compact_pct > 100 && o->compact_pct != PR_COMPACT_NEVER)
+    return set_error(PR_ERR_INVALID_ARG, "compact_pct must be 0, 1..100 or PR_COMPACT_NEVER");
+  if (o->reserved != 0) return set_error(PR_ERR_INVALID_ARG, "reserved must be 0");
   return PR_OK;
 }
 
@@ -333,7 +339,7 @@ namespace pr {
 // table, launch, record the scenes' last-use events.  ``counts_dev`` selects
 // the instrumented kernel.
 pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_scene*>& scenes,
-                          uint32_t total_jobs, int step_budget, bool use_graph,
+                          uint32_t total_jobs, int step_budget, int compact, bool use_graph,
                           unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt) {
   LaunchCtx* c = acquire_ctx((uint32_t)reqs.size());
   if (!c) return set_error(PR_ERR_OUT_OF_MEMORY, "could not allocate a launch context");
@@ -379,6 +385,11 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   q.total_jobs = total_jobs;
   q.n_req = (uint32_t)reqs.size();
   bool shared = !scenes.empty();
+  // scenes with user estimators run their own build, which does not regroup
+  bool user = false;
+  for (pr_scene* s : scenes) user = user || (s->n_types_present >> PR_USER_TYPE_BASE) != 0;
+  if (user) compact = 0;
+  q.compact_pct = (uint32_t)compact;
   for (pr_scene* s : scenes) shared = shared && s == scenes[0];
   if (shared) {
     // one scene for the whole launch: every workgroup stages its top BVH
@@ -393,8 +404,6 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   std::memcpy((char*)c->host + sizeof(QueueDev), table.data(), table.size() * sizeof(ReqDev));
   const size_t bytes = sizeof(QueueDev) + reqs.size() * sizeof(ReqDev);
   // scenes with user estimators run the kernel built with them
-  bool user = false;
-  for (pr_scene* s : scenes) user = user || (s->n_types_present >> PR_USER_TYPE_BASE) != 0;
   UserKernels uk;
   if (user) {
     pr_status st = user_kernels(&uk);
@@ -409,13 +418,14 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     return user ? launch_trace_user(uk, r0, q0, cf, counts, s)
                 : launch_trace(r0, q0, total_jobs, (uint32_t)reqs.size(), cf, counts, s);
   };
-  LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0)};
+  LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0), compact};
   hipError_t e;
   bool graphed = false;
   if (use_graph && stream != nullptr && counts_dev == nullptr) {
     const void* kernel_id = user ? uk.plain : nullptr;
     if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
-          c->graph_budget == step_budget && c->graph_stream == stream && c->graph_kernel == kernel_id)) {
+          c->graph_budget == step_budget && c->graph_stream == stream && c->graph_kernel == kernel_id &&
+          c->graph_compact == compact)) {
       if (c->graph) {
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
@@ -443,6 +453,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
         c->graph_budget = step_budget;
         c->graph_stream = stream;
         c->graph_kernel = kernel_id;
+        c->graph_compact = compact;
       }
     }
     if (c->graph) {
@@ -513,6 +524,15 @@ int budget_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_bud
   return (int)tuned_for(s).step_budget;
 }
 
+// Regrouping threshold of a launch (0 = none) from an explicit request
+// (1..100 or PR_COMPACT_NEVER), else the scene class's tuned choice.
+int compact_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_pct) {
+  const uint32_t v = (o && o->compact_pct) ? o->compact_pct : override_pct;
+  if (v == PR_COMPACT_NEVER) return 0;
+  if (v >= 1 && v <= 100) return (int)v;
+  return (int)tuned_for(s).compact;
+}
+
 }  // namespace pr
 
 extern "C" {
@@ -526,8 +546,8 @@ pr_status pr_render(pr_scene* s, const pr_camera* cam, const pr_render_opts* opt
     pr_status st = add_request(reqs, scenes, s, cam, opts, w, h, out_rgb, out_t, out_inst, 0, total, true);
     if (st != PR_OK) return st;
     std::lock_guard<std::mutex> lk(s->mu);
-    st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), false, nullptr, (hipStream_t)stream,
-                         nullptr);
+    st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), compact_for(s, opts, 0), false, nullptr,
+                         (hipStream_t)stream, nullptr);
     return st == PR_OK ? ok() : st;
   } catch (...) {
     return set_error(PR_ERR_DEVICE, "unexpected exception");
@@ -568,7 +588,8 @@ pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_op
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), false, d, nullptr, nullptr);
+      st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), compact_for(s, opts, 0), false, d,
+                           nullptr, nullptr);
     }
     if (st == PR_OK) {
       e = hipDeviceSynchronize();
@@ -585,10 +606,12 @@ pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_op
 pr_status pr_render_batch(const pr_request* rq, uint32_t n, const pr_batch_opts* bo, void* stream) {
   try {
     if (!rq || n == 0 || n > 4096) return set_error(PR_ERR_INVALID_ARG, "need 1..4096 requests");
-    pr_batch_opts b{0, 0, 0, 0};
+    pr_batch_opts b{0, 0, 0, 0, 0};
     if (bo) b = *bo;
     if ((b.tile_w == 0) != (b.tile_h == 0) || (b.tile_w && b.tile_w * b.tile_h != 64))
       return set_error(PR_ERR_INVALID_ARG, "batch tile must be 0,0 or multiply to 64");
+    if (b.compact_pct > 100 && b.compact_pct != PR_COMPACT_NEVER)
+      return set_error(PR_ERR_INVALID_ARG, "compact_pct must be 0, 1..100 or PR_COMPACT_NEVER");
     std::vector<ReqDev> reqs;
     std::vector<pr_scene*> scenes;
     reqs.reserve(n);
@@ -602,8 +625,8 @@ pr_status pr_render_batch(const pr_request* rq, uint32_t n, const pr_batch_opts*
       }
     }
     int budget = b.step_budget ? (int)b.step_budget : budget_for(scenes[0], nullptr, 0);
-    pr_status st = launch_prepared(reqs, scenes, total, budget, b.use_graph != 0, nullptr, (hipStream_t)stream,
-                                   nullptr);
+    pr_status st = launch_prepared(reqs, scenes, total, budget, compact_for(scenes[0], nullptr, b.compact_pct),
+                                   b.use_graph != 0, nullptr, (hipStream_t)stream, nullptr);
     return st == PR_OK ? ok() : st;
   } catch (...) {
     return set_error(PR_ERR_DEVICE, "unexpected exception");
@@ -615,6 +638,7 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
     if (!rq || n == 0 || n > 4096) return set_error(PR_ERR_INVALID_ARG, "need 1..4096 requests");
     static const uint32_t tiles[] = {8, 16, 32, 64};
     static const uint32_t budgets[] = {8, 16, 24, 32, 64};
+    static const uint32_t compacts[] = {PR_COMPACT_NEVER, 50, 100};
     hipStream_t st_ = nullptr;
     hipError_t e = hipStreamCreate(&st_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -629,10 +653,10 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
       return hip_fail(e, "hipEventCreate");
     }
     float best_ms = 1e30f;
-    pr_batch_opts best{8, 8, 16, 0};
+    pr_batch_opts best{8, 8, 16, 0, PR_COMPACT_NEVER};
     for (uint32_t tw : tiles) {
-      for (uint32_t sb : budgets) {
-        pr_batch_opts o{tw, 64 / tw, sb, 0};
+      for (uint32_t sb : budgets) for (uint32_t cp : compacts) {
+        pr_batch_opts o{tw, 64 / tw, sb, 0, cp};
         // warm-up then 3 timed launches, take the minimum
         pr_status s = pr_render_batch(rq, n, &o, st_);
         if (s != PR_OK) {
@@ -666,7 +690,8 @@ pr_status pr_autotune(const pr_request* rq, uint32_t n, pr_batch_opts* best_out)
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       load_tune_cache();
-      g_tuned[size_class(rq[0].scene)] = Tuned{best.tile_w, best.step_budget};
+      g_tuned[size_class(rq[0].scene)] =
+          Tuned{best.tile_w, best.step_budget, best.compact_pct == PR_COMPACT_NEVER ? 0u : best.compact_pct};
       save_tune_cache();
     }
     if (best_out) *best_out = best;

@@ -392,7 +392,8 @@ static_assert(sizeof(pr_instance) == 56, "pr_instance layout");
 static_assert(sizeof(pr_material) == 16, "pr_material layout");
 static_assert(sizeof(pr_scene_consts) == 40, "pr_scene_consts layout");
 static_assert(sizeof(pr_camera) == 40, "pr_camera layout");
-static_assert(sizeof(pr_render_opts) == 64, "pr_render_opts layout");
+static_assert(sizeof(pr_render_opts) == 72, "pr_render_opts layout");
+static_assert(sizeof(pr_batch_opts) == 20, "pr_batch_opts layout");
 
 extern "C" {
 

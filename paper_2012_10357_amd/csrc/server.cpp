@@ -28,13 +28,14 @@
 
 namespace pr {
 pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_scene*>& scenes,
-                          uint32_t total_jobs, int step_budget, bool use_graph,
+                          uint32_t total_jobs, int step_budget, int compact, bool use_graph,
                           unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt);
 pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes, pr_scene* s,
                       const pr_camera* cam, const pr_render_opts* o, uint32_t w, uint32_t h, float* rgb,
                       float* t, int32_t* inst, uint32_t tile_w_override, uint32_t& total_jobs,
                       bool check_ptrs);
 int budget_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_budget);
+int compact_for(const pr_scene* s, const pr_render_opts* o, uint32_t override_pct);
 }  // namespace pr
 
 using namespace pr;
@@ -162,7 +163,8 @@ class HipExecutor : public Executor {
       }
     }
     int budget = budget_for(scenes[0], nullptr, 0);
-    return launch_prepared(reqs, scenes, total, budget, graph_, nullptr, streams_[slot], events_[slot]);
+    return launch_prepared(reqs, scenes, total, budget, compact_for(scenes[0], nullptr, 0), graph_, nullptr,
+                           streams_[slot], events_[slot]);
   }
   bool done(int slot) override { return hipEventQuery(events_[slot]) != hipErrorNotReady; }
   void shutdown() override {

@@ -147,8 +147,31 @@ __device__ __forceinline__ float triangle_hit(const InstDev& I, float ox, float 
   return in ? t : __builtin_inff();
 }
 
-// The whole path for one workgroup; the kernels below wrap it.
-template <bool COUNT>
+// Sphere-trace query of one (ray, instance) pair, kept in LDS in a slot per
+// lane, one field per row (structure of arrays, so the lanes of a wave touch
+// consecutive words): the local ray, the march interval, the instance
+// record's address, and a word packing the steps taken (bits 0-12), the
+// march's state (bits 13-14) and the request index (bits 16-31).  A lane
+// waiting for a normal keeps its hit in the same slot: local ray, hit
+// distance, and the difference step in Q_T1.  Keeping this state in LDS
+// rather than registers leaves the registers to the estimators, and lets any
+// lane of the workgroup march any query.
+constexpr int Q_OX = 0, Q_DX = 3, Q_T = 6, Q_T1 = 7, Q_PLO = 8, Q_PHI = 9, Q_META = 10, kQF = 11;
+constexpr uint32_t S_CONT = 0, S_HIT = 1, S_MISS = 2;
+constexpr int kTypeKeys = 8;                            // procedural types and the triangle tag
+
+// The cutting plane of an instance along a local ray: n.(o' + t d') - d =
+// x + t y, with x = -inf when the instance has no cut.
+__device__ __forceinline__ float2 cut_line_of(const InstDev& I, const float ol[3], const float dl[3]) {
+  const bool has_cut = I.cut[0] != 0.f || I.cut[1] != 0.f || I.cut[2] != 0.f;
+  const float cx = I.cut[0] * ol[0] + I.cut[1] * ol[1] + I.cut[2] * ol[2] - I.cut[3];
+  const float cy = I.cut[0] * dl[0] + I.cut[1] * dl[1] + I.cut[2] * dl[2];
+  return make_float2(has_cut ? cx : -__builtin_inff(), cy);
+}
+
+// The whole path for one workgroup; the kernels below wrap it.  POOL selects
+// the regrouping variant (see the burst below).
+template <bool COUNT, bool POOL>
 __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue,
                                            int step_budget, unsigned long long* __restrict__ counts) {
   __shared__ uint16_t stack_mem[kStackDepth][kBlock];
@@ -157,14 +180,15 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   __shared__ InstDev lds_insts[kLdsInsts];
   __shared__ ReqDev lds_reqs[kLdsReqs];
   __shared__ SceneConstsDev lds_consts;
-  // pooled normal taps: a lane waiting for a normal posts its local hit point
-  // (FP64), step and instance record; one wave-wide pass then evaluates the
-  // six taps of up to ten pending normals, one tap per lane
-  __shared__ double nrm_pt[kWavesPerBlock][3][kWave];
-  __shared__ float nrm_h[kWavesPerBlock][kWave];
-  __shared__ const InstDev* nrm_inst[kWavesPerBlock][kWave];
+  // query slots (see Q_*); pooled normal taps: lanes waiting for a normal
+  // list themselves, then one wave-wide pass evaluates the six taps of up to
+  // ten pending normals, one tap per lane, from the owners' slots
+  __shared__ float qs[kQF][kBlock];
   __shared__ float nrm_res[kWavesPerBlock][6][kWave];
   __shared__ uint8_t nrm_owner[kWavesPerBlock][kWave];
+  // regrouping variant: per type key, the set of slots whose query waits to
+  // be marched (256 bits as 8 words)
+  __shared__ uint32_t pend[POOL ? kTypeKeys : 1][POOL ? 8 : 1];
   // Shadow rays of primary hits that go on to a mirror bounce are handed to
   // idle lanes of the same wave, so the shadow ray and the bounce chain run
   // side by side.  Slot = owner lane: shadow-ray origin and Lambert factor,
@@ -173,9 +197,6 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   __shared__ uint32_t tk_ref[kWavesPerBlock][kWave];
   __shared__ uint32_t tk_state[kWavesPerBlock][kWave];
   __shared__ uint8_t tk_list[kWavesPerBlock][kWave];
-  // cutting plane of the candidate being marched, along its local ray:
-  // n.(o' + t d') - d = x + t y; x = -inf when the instance has no cut
-  __shared__ float2 cut_line[kBlock];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
@@ -225,11 +246,9 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   // current march / normal evaluation
   int cur_slot = -1;
   uint32_t cur_type = 0;
-  float prm[6];
-  float lo_[3], ld_[3];
-  float t = 0.f, t1 = 0.f, sigma = 1.f;
-  int steps = 0;
+  float t = 0.f;
   uint32_t job_evals = 0;   // estimator evaluations of the current pixel job
+  uint32_t march_steps = 0; // steps of the current march already counted in job_evals
   int help_owner = -1;      // K_HSHADOW: lane whose primary hit this shadow ray serves
   bool donated = false;     // this lane's primary shadow ray was handed off
   float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -261,6 +280,35 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   };
   uint32_t max_steps = 1;
   float eps = 1e-4f;
+
+  // post this lane's query (or waiting hit) to its slot
+  auto q_post = [&](const InstDev* ip, const float* ol, const float* dl, float a, float b)
+                    __attribute__((always_inline)) {
+    qs[Q_OX + 0][tid] = ol[0];
+    qs[Q_OX + 1][tid] = ol[1];
+    qs[Q_OX + 2][tid] = ol[2];
+    qs[Q_DX + 0][tid] = dl[0];
+    qs[Q_DX + 1][tid] = dl[1];
+    qs[Q_DX + 2][tid] = dl[2];
+    qs[Q_T][tid] = a;
+    qs[Q_T1][tid] = b;
+    const uint64_t pv = (uint64_t)(uintptr_t)ip;
+    qs[Q_PLO][tid] = __uint_as_float((uint32_t)pv);
+    qs[Q_PHI][tid] = __uint_as_float((uint32_t)(pv >> 32));
+    qs[Q_META][tid] = __uint_as_float(req_i << 16);
+  };
+
+  // the query in this lane's slot starts marching; the regrouping variant
+  // also offers it to every wave of the workgroup
+  auto start_march = [&]() __attribute__((always_inline)) {
+    march_steps = 0;
+    mode = M_MARCH;
+    if constexpr (POOL) {
+      const uint32_t key = cur_type < (uint32_t)kTypeKeys ? cur_type : (uint32_t)kTypeKeys - 1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      atomicOr(&pend[key][tid >> 5], 1u << (tid & 31));
+    }
+  };
 
   unsigned long long c_nodes = 0, c_clips = 0;
   uint32_t res_cur = 0, res_end = 0;   // this wave's reservation of job indices (wave-uniform)
@@ -418,12 +466,9 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       if (!(th >= tmin && th <= limit)) return false;
       cur_slot = slot;
       cur_type = kTriangle;
-      sigma = 1.f;
-      t = th;
-      t1 = th;
-      steps = 0;
-      cut_line[tid] = make_float2(-__builtin_inff(), 0.f);
-      mode = M_MARCH;
+      const float z3[3] = {0.f, 0.f, 0.f};
+      q_post(&I, z3, z3, th, th);
+      start_march();
       return true;
     }
     float d0 = ray.ox - I.b[0], d1 = ray.oy - I.b[1], d2 = ray.oz - I.b[2];
@@ -440,21 +485,8 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     if (!local_slab(ol, dl, lo, hi, tmin, limit, a0, a1)) return false;
     cur_slot = slot;
     cur_type = I.type;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) prm[i] = I.prm[i];
-    lo_[0] = ol[0]; lo_[1] = ol[1]; lo_[2] = ol[2];
-    ld_[0] = dl[0]; ld_[1] = dl[1]; ld_[2] = dl[2];
-    sigma = I.sigma;
-    {
-      const bool has_cut = I.cut[0] != 0.f || I.cut[1] != 0.f || I.cut[2] != 0.f;
-      const float cx = I.cut[0] * ol[0] + I.cut[1] * ol[1] + I.cut[2] * ol[2] - I.cut[3];
-      const float cy = I.cut[0] * dl[0] + I.cut[1] * dl[1] + I.cut[2] * dl[2];
-      cut_line[tid] = make_float2(has_cut ? cx : -__builtin_inff(), cy);
-    }
-    t = a0;
-    t1 = a1;
-    steps = 0;
-    mode = M_MARCH;
+    q_post(&I, ol, dl, a0, a1);
+    start_march();
     return true;
   };
 
@@ -531,12 +563,8 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     float dl0 = I.Ainv[0] * ray.dx + I.Ainv[1] * ray.dy + I.Ainv[2] * ray.dz;
     float dl1 = I.Ainv[3] * ray.dx + I.Ainv[4] * ray.dy + I.Ainv[5] * ray.dz;
     float dl2 = I.Ainv[6] * ray.dx + I.Ainv[7] * ray.dy + I.Ainv[8] * ray.dz;
-    const double tt = (double)th;
-    nrm_pt[wv][0][lane] = (double)ol0 + tt * (double)dl0;
-    nrm_pt[wv][1][lane] = (double)ol1 + tt * (double)dl1;
-    nrm_pt[wv][2][lane] = (double)ol2 + tt * (double)dl2;
-    nrm_h[wv][lane] = R->fd_h / I.sigma;
-    nrm_inst[wv][lane] = ip;
+    const float ol[3] = {ol0, ol1, ol2}, dl[3] = {dl0, dl1, dl2};
+    q_post(ip, ol, dl, th, R->fd_h / I.sigma);
     cur_slot = slot;
     t = th;
     mode = M_NORMAL;
@@ -769,7 +797,165 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   };
 
+  // a march stopped with v < eps at t: record the hit
+  auto record_hit = [&]() __attribute__((always_inline)) {
+    if (kind & 1u) {
+      occluded = true;
+      mode = M_RAYDONE;
+    } else {
+      // closest hit: lexicographic minimum of (t, instance index)
+      const uint32_t u = __float_as_uint(inst_ptr(cur_slot)->prm[7]);
+      if (best_slot < 0 || t < limit || (t == limit && u < best_uid)) {
+        limit = t;
+        best_slot = cur_slot;
+        best_uid = u;
+      }
+      mode = M_TRAVERSE;
+    }
+  };
+
+  // A burst of up to step_budget lock-step estimator evaluations of the query
+  // in slot q (for lanes with act): v = sigma DE(o' + t d'); hit if v < eps,
+  // else t += v; miss once t passes t1 or the step budget is spent, or on a
+  // NaN.  The burst ends once fewer than an eighth of end_n queries still
+  // march: a control phase costs about four steps, so lanes that have
+  // finished wait a few steps rather than forcing one.  The outcome and the
+  // steps taken go back to the slot; returns the query's state.
+  auto march_query = [&](bool act, int q, int end_n) __attribute__((always_inline)) -> uint32_t {
+    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tq = 0.f, t1q = 0.f, sg = 1.f;
+    float kp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float2 cl = make_float2(-__builtin_inff(), 0.f);
+    uint32_t meta = 0, ty = kTriangle;
+    float eq = 1.f;
+    int mq = 1;
+    if (act) {
+      ox = qs[Q_OX + 0][q]; oy = qs[Q_OX + 1][q]; oz = qs[Q_OX + 2][q];
+      dx = qs[Q_DX + 0][q]; dy = qs[Q_DX + 1][q]; dz = qs[Q_DX + 2][q];
+      tq = qs[Q_T][q];
+      t1q = qs[Q_T1][q];
+      meta = __float_as_uint(qs[Q_META][q]);
+      const InstDev* ip = (const InstDev*)(uintptr_t)((uint64_t)__float_as_uint(qs[Q_PLO][q]) |
+                                                      ((uint64_t)__float_as_uint(qs[Q_PHI][q]) << 32));
+      ty = ip->type;
+      if (ty != kTriangle) {
+        sg = ip->sigma;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) kp[i] = ip->prm[i];
+        const float o3[3] = {ox, oy, oz}, d3[3] = {dx, dy, dz};
+        cl = cut_line_of(*ip, o3, d3);
+      }
+      const uint32_t rq = meta >> 16;
+      const ReqDev* Rq = rq < kLdsReqs ? &lds_reqs[rq] : reqs + rq;
+      eq = Rq->eps;
+      mq = (int)Rq->max_steps;
+    }
+    int sq = (int)(meta & 0x1fffu);
+    uint32_t st = S_CONT;
+    const bool qcut = __ballot(act && cl.x != -__builtin_inff()) != 0ull;
+    for (int it = 0; it < step_budget; ++it) {
+      if (act && st == S_CONT) {
+        const float qx = ox + tq * dx;
+        const float qy = oy + tq * dy;
+        const float qz = oz + tq * dz;
+        int iters = 0;
+        float de = 0.f;  // a triangle's hit was found in closed form: a zero estimate
+        if (ty != kTriangle) de = de_eval(ty, qx, qy, qz, kp, &iters);
+        if (qcut) {
+          if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + tq * cl.y);
+        }
+        if constexpr (COUNT) if (ty < PR_NUM_TYPES) {
+          atomicAdd(&cnt_lds[ty], 1ull);
+          atomicAdd(&cnt_lds[7 + ty], (unsigned long long)iters);
+        }
+        const float v = sg * de;
+        const bool step = v >= eq;
+        tq = step ? tq + v : tq;
+        sq += step ? 1 : 0;
+        if (!step || tq > t1q || sq >= mq) st = v < eq ? S_HIT : S_MISS;
+      }
+      const unsigned long long still = __ballot(act && st == S_CONT);
+      if (still == 0ull || 8 * __popcll(still) < end_n) break;
+    }
+    if (act) {
+      qs[Q_T][q] = tq;
+      if constexpr (POOL) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      qs[Q_META][q] = __uint_as_float((meta & 0xffff0000u) | (st << 13) | (uint32_t)sq);
+    }
+    return st;
+  };
+
+  // regrouping variant: queries a wave claims per burst, compact_pct % of 64
+  const uint32_t claim_cap = POOL ? max(1u, min(64u, (queue->compact_pct * 64u + 99u) / 100u)) : 64u;
+
+  // Regrouping variant: the wave takes up to claim_cap waiting queries of the type
+  // key that has the most (the higher key on a tie: the fractals), from any wave of the
+  // workgroup, marches them in one burst, and offers the unfinished ones
+  // again.  The waiting sets are words of LDS bits claimed by atomic
+  // exchange, so no wave ever waits for another; a query is marched by one
+  // wave at a time, and each (ray, instance) march is the same sequence as
+  // in its own lane.
+  auto pool_burst = [&]() __attribute__((always_inline)) {
+    // lanes 8 k .. 8 k + 7 read the 8 words of key k
+    const uint32_t word = pend[lane >> 3][lane & 7];
+    uint32_t c = (uint32_t)__popc(word);
+    c += (uint32_t)__shfl_xor((int)c, 1);
+    c += (uint32_t)__shfl_xor((int)c, 2);
+    c += (uint32_t)__shfl_xor((int)c, 4);
+    uint32_t score = (c << 3) | (uint32_t)(lane >> 3);
+    score = max(score, (uint32_t)__shfl_xor((int)score, 8));
+    score = max(score, (uint32_t)__shfl_xor((int)score, 16));
+    score = max(score, (uint32_t)__shfl_xor((int)score, 32));
+    if ((score >> 3) == 0u) {
+      __builtin_amdgcn_s_sleep(1);   // every waiting query is being marched elsewhere
+      return;
+    }
+    const uint32_t k = score & 7u;
+    uint32_t got = lane < 8 ? atomicExch(&pend[k][lane], 0u) : 0u;
+    const uint32_t cnt = (uint32_t)__popc(got);
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)inc, d);
+      if (lane >= d) inc += v;
+    }
+    const uint32_t exc = inc - cnt;
+    const uint32_t keep = exc < claim_cap ? min(cnt, claim_cap - exc) : 0u;
+    if (lane < 8 && keep < cnt) {
+      // give back the claimed bits past the first `keep` ones
+      uint32_t back = got;
+      for (uint32_t i = 0; i < keep; ++i) back &= back - 1u;
+      atomicOr(&pend[k][lane], back);
+      got &= ~back;
+    }
+    const uint32_t n_take = min((uint32_t)__shfl((int)inc, 7), claim_cap);
+    // lane j takes the j-th kept query in slot order
+    uint32_t myw = 0, wi = 0, r = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint32_t gw = (uint32_t)__shfl((int)got, w), ew = (uint32_t)__shfl((int)exc, w);
+      const uint32_t kw = (uint32_t)__popc(gw);
+      if ((uint32_t)lane >= ew && (uint32_t)lane < ew + kw) {
+        myw = gw;
+        wi = (uint32_t)w;
+        r = (uint32_t)lane - ew;
+      }
+    }
+    for (uint32_t i = 0; i < r; ++i) myw &= myw - 1u;
+    const bool act = (uint32_t)lane < n_take;
+    const int q = act ? (int)(wi * 32u + (uint32_t)__ffs(myw) - 1u) : tid;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t st = march_query(act, q, (int)n_take);
+    if (act && st == S_CONT) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      atomicOr(&pend[k][q >> 5], 1u << (q & 31));
+    }
+  };
+
   // ---------------- main loop
+  if constexpr (POOL) {
+    if (tid < kTypeKeys * 8) pend[tid >> 3][tid & 7] = 0u;
+    __syncthreads();
+  }
   tk_state[wv][lane] = T_NONE;
   for (;;) {
     // owners waiting for a handed-off shadow ray; then idle lanes take the
@@ -840,6 +1026,24 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       }
     }
 
+    // marching lanes take their march's progress and outcome from their slots
+    if (has_job && mode == M_MARCH) {
+      const uint32_t meta = __float_as_uint(qs[Q_META][tid]);
+      const uint32_t st = (meta >> 13) & 3u, sn = meta & 0x1fffu;
+      job_evals += sn - march_steps;
+      march_steps = sn;
+      if (st != S_CONT) {
+        if constexpr (POOL) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (st == S_HIT) {
+          ++job_evals;
+          t = qs[Q_T][tid];
+          record_hit();
+        } else {
+          mode = M_TRAVERSE;
+        }
+      }
+    }
+
     // control: advance every lane to its next estimator evaluation
     auto control = [&]() __attribute__((always_inline)) {
       while (has_job && mode != M_MARCH && mode != M_NORMAL && mode != M_WAIT) {
@@ -876,16 +1080,24 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         if (j < n_taps) {
           const uint32_t owner = nrm_owner[wv][j / 6];
           const uint32_t tap = j % 6, ax = tap >> 1;
-          const double h = (tap & 1) ? -(double)nrm_h[wv][owner] : (double)nrm_h[wv][owner];
-          const InstDev* ip = nrm_inst[wv][owner];
+          // the owner's hit: local ray, distance and step from its slot; the
+          // hit point in FP64
+          const int os = wv * kWave + (int)owner;
+          const double tt = (double)qs[Q_T][os];
+          const double px_ = (double)qs[Q_OX + 0][os] + tt * (double)qs[Q_DX + 0][os];
+          const double py_ = (double)qs[Q_OX + 1][os] + tt * (double)qs[Q_DX + 1][os];
+          const double pz_ = (double)qs[Q_OX + 2][os] + tt * (double)qs[Q_DX + 2][os];
+          const double h = (tap & 1) ? -(double)qs[Q_T1][os] : (double)qs[Q_T1][os];
+          const InstDev* ip = (const InstDev*)(uintptr_t)((uint64_t)__float_as_uint(qs[Q_PLO][os]) |
+                                                          ((uint64_t)__float_as_uint(qs[Q_PHI][os]) << 32));
           float kp[6];
 #pragma unroll
           for (int i = 0; i < 6; ++i) kp[i] = ip->prm[i];
           const uint32_t ty = ip->type;
           int iters;
-          const double qx = nrm_pt[wv][0][owner] + (ax == 0 ? h : 0.0);
-          const double qy = nrm_pt[wv][1][owner] + (ax == 1 ? h : 0.0);
-          const double qz = nrm_pt[wv][2][owner] + (ax == 2 ? h : 0.0);
+          const double qx = px_ + (ax == 0 ? h : 0.0);
+          const double qy = py_ + (ax == 1 ? h : 0.0);
+          const double qz = pz_ + (ax == 2 ? h : 0.0);
           double v = de_eval64(ty, qx, qy, qz, kp, &iters);
           const float* cu = ip->cut;
           if (cu[0] != 0.f || cu[1] != 0.f || cu[2] != 0.f) {
@@ -929,62 +1141,11 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       __builtin_amdgcn_s_setprio(0);
     }
 
-    // A cut is only set by the control phase, so one test per burst tells
-    // whether any marching lane of the wave needs it.
-    const bool wave_cut =
-        __ballot(has_job && mode == M_MARCH && cut_line[tid].x != -__builtin_inff()) != 0ull;
-    const int busy_n = __popcll(busy);
-
-    // burst of lock-step estimator evaluations
-    for (int it = 0; it < step_budget; ++it) {
-      if (has_job && mode == M_MARCH) {
-        const float qx = lo_[0] + t * ld_[0];
-        const float qy = lo_[1] + t * ld_[1];
-        const float qz = lo_[2] + t * ld_[2];
-        int iters = 0;
-        float de = 0.f;  // a triangle's hit was found in closed form: a zero estimate
-        if (cur_type != kTriangle) {
-          de = de_eval(cur_type, qx, qy, qz, prm, &iters);
-        }
-        if (wave_cut) {
-          const float2 cl = cut_line[tid];
-          if (cl.x != -__builtin_inff() && de == de) de = fmaxf(de, cl.x + t * cl.y);
-        }
-        ++job_evals;
-        if constexpr (COUNT) if (cur_type < PR_NUM_TYPES) {
-          atomicAdd(&cnt_lds[cur_type], 1ull);
-          atomicAdd(&cnt_lds[7 + cur_type], (unsigned long long)iters);
-        }
-        const float v = sigma * de;
-        // the common case, a step, without branches; false for a hit and NaN
-        const bool step = v >= eps;
-        t = step ? t + v : t;
-        steps += step ? 1 : 0;
-        if (!step || t > t1 || steps >= (int)max_steps) {
-          if (v < eps) {
-            // hit at t
-            if (kind & 1u) {
-              occluded = true;
-              mode = M_RAYDONE;
-            } else {
-              // closest hit: lexicographic minimum of (t, instance index)
-              const uint32_t u = __float_as_uint(inst_ptr(cur_slot)->prm[7]);
-              if (best_slot < 0 || t < limit || (t == limit && u < best_uid)) {
-                limit = t;
-                best_slot = cur_slot;
-                best_uid = u;
-              }
-              mode = M_TRAVERSE;
-            }
-          } else {
-            mode = M_TRAVERSE;  // left the box, out of steps, or NaN (a miss)
-          }
-        }
-      }
-      // end the burst once fewer than an eighth of the busy lanes still
-      // march: a control phase costs about as much as four steps, so lanes
-      // that have finished wait a few steps rather than being refilled
-      if (8 * __popcll(__ballot(has_job && mode == M_MARCH)) < busy_n) break;
+    if constexpr (POOL) {
+      pool_burst();
+    } else {
+      const bool marching = has_job && mode == M_MARCH;
+      if (__ballot(marching)) march_query(marching, tid, __popcll(busy));
     }
   }
 
@@ -1000,11 +1161,11 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
 
 #ifndef PR_USER_ESTIMATORS
 
-template <bool COUNT>
+template <bool COUNT, bool POOL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(
     const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  trace_body<COUNT>(reqs, queue, step_budget, counts);
+  trace_body<COUNT, POOL>(reqs, queue, step_budget, counts);
 }
 
 int device_cu_count() {
@@ -1016,7 +1177,7 @@ int device_cu_count() {
 
 int occupancy_blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<false>, kBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<false, false>, kBlock, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -1026,13 +1187,10 @@ int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_job
   (void)total_jobs;
   (void)n_req;
   dim3 grid(cfg.grid_blocks), block(kBlock);
-  if (counts_dev) {
-    hipLaunchKernelGGL(trace_kernel<true>, grid, block, 0, (hipStream_t)stream, reqs_dev,
-                       queue_dev, cfg.step_budget, counts_dev);
-  } else {
-    hipLaunchKernelGGL(trace_kernel<false>, grid, block, 0, (hipStream_t)stream, reqs_dev,
-                       queue_dev, cfg.step_budget, counts_dev);
-  }
+  // the queue header carries the same compact_pct; it selects the kernel
+  auto k = counts_dev ? (cfg.compact_pct > 0 ? trace_kernel<true, true> : trace_kernel<true, false>)
+                      : (cfg.compact_pct > 0 ? trace_kernel<false, true> : trace_kernel<false, false>);
+  hipLaunchKernelGGL(k, grid, block, 0, (hipStream_t)stream, reqs_dev, queue_dev, cfg.step_budget, counts_dev);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1046,11 +1204,11 @@ int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_job
 extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user(
     const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  pr::trace_body<false>(reqs, queue, step_budget, counts);
+  pr::trace_body<false, false>(reqs, queue, step_budget, counts);
 }
 extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user_count(
     const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  pr::trace_body<true>(reqs, queue, step_budget, counts);
+  pr::trace_body<true, false>(reqs, queue, step_budget, counts);
 }
 #endif

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == P.PR_ABI_VERSION == 6
+    assert P.abi_version() == P.PR_ABI_VERSION == 7
     assert P.device_count() >= 0
 
 
@@ -120,6 +120,13 @@ def test_render_argument_errors_before_device(P):
     oc.flags = 2
     st = P.lib().pr_render(sc.handle, C.byref(P.camera_c(cam)), C.byref(oc), 64, 64, None, None, None, None)
     assert st == P.PR_ERR_INVALID_ARG and b"flags" in P.lib().pr_last_error()
+    for cp in (101, 999, 1001):
+        with pytest.raises(P.ProcrayError, match="compact_pct"):
+            P.render(sc, cam, o, fake, compact=cp)
+    oc = P.opts_c(o)
+    oc.reserved = 1
+    st = P.lib().pr_render(sc.handle, C.byref(P.camera_c(cam)), C.byref(oc), 64, 64, None, None, None, None)
+    assert st == P.PR_ERR_INVALID_ARG and b"reserved" in P.lib().pr_last_error()
     # host-only build: not uploaded, so rendering is refused before any device call
     with pytest.raises(P.ProcrayError, match="NOT_BUILT"):
         P.render(sc, cam, o, fake)

@@ -193,3 +193,62 @@ def test_counts_match_oracle_work():
     it_g, it_o = c[7:14].sum(), float(sum(orc["iters"]))
     assert abs(it_g - it_o) / it_o < 0.1
     assert np.array_equal(c[14:21], np.array(orc["normal_evals"], np.float64))
+
+
+def _regroup_cases():
+    import dataclasses
+    c2 = W.c2(320, 180)
+    c3 = W.c3()
+    f2 = W.f2_sample()
+    f1 = W.f1_julia_cut(160, 90)
+    dense = W.random_instances_scene(np.random.default_rng(8), 600, W.C5_KINDS)
+    return {
+        "teaser + bounce": (c2.scenes[0], c2.requests[0].camera, c2.requests[0].opts),
+        "c3 dense 2 spp": (c3.scenes[0], c3.requests[0].camera,
+                           dataclasses.replace(c3.requests[0].opts, width=256, height=144, spp=2)),
+        "c5 kinds 3 spp": (dense, W.camera((0.0, 5.0, -50.0)),
+                           W.RenderOpts(192, 108, spp=3, jitter=1, seed=4, max_steps=256, tmax=200.0)),
+        "sample scene with plane": (f2.scenes[0], f2.requests[0].camera,
+                                    dataclasses.replace(f2.requests[0].opts, width=160, height=90)),
+        "oblique julia cut": (f1.scenes[f1.requests[1].scene_index], f1.requests[1].camera, f1.requests[1].opts),
+    }
+
+
+@pytest.mark.parametrize("case", list(_regroup_cases().keys()))
+def test_regrouping_invariance(case):
+    """Pooling a workgroup's sphere-trace queries by primitive type (any
+    threshold, tile, budget; single render, batch with graph replay, the
+    allocation-free path) gives the bits of waves marching their own lanes,
+    and the instrumented build counts the same work."""
+    P = require_gpu()
+    import torch
+    desc, cam, opts = _regroup_cases()[case]
+    sc = P.Scene(desc)
+
+    def run(**kw):
+        rgb, t, inst = alloc(opts.width, opts.height)
+        P.render(sc, cam, opts, rgb, t, inst, **kw)
+        torch.cuda.synchronize()
+        return rgb.cpu().numpy(), t.cpu().numpy(), inst.cpu().numpy()
+
+    ref = run(compact=P.PR_COMPACT_NEVER)
+    assert (ref[2] >= 0).any()
+    for cp in (1, 50, 100):
+        _eq(ref, run(compact=cp))
+    _eq(ref, run(compact=100, tile=(16, 4), step_budget=5))
+    _eq(ref, run(compact=30, tile=(64, 1), step_budget=64))
+    out = alloc(opts.width, opts.height)
+    reqs = P.make_requests([(sc, cam, opts, *out, 0)])
+    for _ in range(2):
+        P.render_batch(reqs, use_graph=True, compact=100, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        _eq(ref, [x.cpu().numpy() for x in out])
+    na = alloc(opts.width, opts.height)
+    P.render_noalloc(sc, cam, opts, *na, compact=100)
+    torch.cuda.synchronize()
+    _eq(ref, [x.cpu().numpy() for x in na])
+    rgb = torch.empty((opts.height, opts.width, 3), device="cuda")
+    c_plain = P.render_counts(sc, cam, opts, rgb, compact=P.PR_COMPACT_NEVER)
+    c_pool = P.render_counts(sc, cam, opts, rgb, compact=100)
+    assert np.array_equal(c_plain, c_pool), (c_plain, c_pool)
+    sc.close()
