@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 7
+#define PR_ABI_VERSION 8
 
 typedef enum {
   PR_OK = 0,
@@ -355,12 +355,14 @@ typedef struct {
   uint32_t use_graph;          /* replay captured graphs for launches */
 } pr_server_opts;
 
+/* rays_shadow counts the shadow rays of primary and bounce hits, rays_bounce
+ * the mirror-bounce rays (both counted on the device as the request runs). */
 typedef struct {
   pr_status status;
   const float* rgb; const float* t; const int32_t* inst;  /* device, valid until release */
   uint32_t width, height;
   double t_submit, t_admit, t_launch, t_done;             /* seconds, steady clock */
-  uint64_t rays_primary, user_tag;
+  uint64_t rays_primary, rays_shadow, rays_bounce, user_tag;
 } pr_request_result;
 
 typedef struct {
@@ -372,7 +374,10 @@ typedef struct {
  * FIFO while their footprint (outputs, plus the per-sample scratch of
  * requests with spp > 1) fits the budget, launches the admitted
  * ones together on a free stream while earlier launches are still running,
- * and records completion times.  Scenes stay resident on the device. */
+ * and records completion times.  A request completes when its own pixels
+ * are done -- the device sets a flag in pinned host memory that the
+ * scheduler polls -- so it can be waited for and released while the rest of
+ * its launch still runs.  Scenes stay resident on the device. */
 pr_status pr_server_create(const pr_server_opts* opts, pr_server** out);
 /* The same scheduler driven by a simulated device: a launch "completes"
  * 20 us + us_per_mpix microseconds per million pixel-samples after it

@@ -109,7 +109,8 @@ class RequestResult(C.Structure):
     _fields_ = [("status", C.c_int), ("rgb", C.c_void_p), ("t", C.c_void_p), ("inst", C.c_void_p),
                 ("width", C.c_uint32), ("height", C.c_uint32), ("t_submit", C.c_double),
                 ("t_admit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double),
-                ("rays_primary", C.c_uint64), ("user_tag", C.c_uint64)]
+                ("rays_primary", C.c_uint64), ("rays_shadow", C.c_uint64), ("rays_bounce", C.c_uint64),
+                ("user_tag", C.c_uint64)]
 
 
 class ServerStats(C.Structure):
@@ -123,7 +124,7 @@ assert C.sizeof(SceneConsts) == 40 and C.sizeof(CameraC) == 40 and C.sizeof(Rend
 assert C.sizeof(BvhNode) == 32
 
 # The C ABI revision these ctypes layouts and signatures describe.
-PR_ABI_VERSION = 7
+PR_ABI_VERSION = 8
 
 _lib = None
 

@@ -126,9 +126,25 @@ struct alignas(16) QueueDev {
   const NodeDev* stage_nodes;     // global source of the staged scene
   const InstDev* stage_insts;
   const SceneConstsDev* stage_consts;
+  // per-request completion tracking (served launches; null otherwise):
+  // device counters, 3 per request (jobs done, shadow rays, bounce rays),
+  // zero at launch, and host-visible completion records
+  unsigned long long* track;
+  struct DoneRec* done_recs;
   const void* pad3;
 };
-static_assert(sizeof(QueueDev) == 64, "queue header");
+static_assert(sizeof(QueueDev) == 80, "queue header");
+
+// Completion record of one tracked request, in host-visible (pinned) memory:
+// the device writes the request's ray counts and then sets done, once every
+// job of the request has finished and its pixels are written.
+struct alignas(16) DoneRec {
+  unsigned long long rays_shadow;   // shadow rays of primary and bounce hits
+  unsigned long long rays_bounce;   // mirror-bounce rays
+  uint32_t done;
+  uint32_t pad[3];
+};
+static_assert(sizeof(DoneRec) == 32, "completion record");
 
 constexpr uint32_t kLdsNodes = 128;   // 8 KB: the top seven BVH levels (breadth-first layout)
 constexpr uint32_t kLdsInsts = 32;    // 4 KB of instance records

@@ -340,7 +340,8 @@ namespace pr {
 // the instrumented kernel.
 pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_scene*>& scenes,
                           uint32_t total_jobs, int step_budget, int compact, bool use_graph,
-                          unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt) {
+                          unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt,
+                          unsigned long long* track_dev, DoneRec* done_host) {
   LaunchCtx* c = acquire_ctx((uint32_t)reqs.size());
   if (!c) return set_error(PR_ERR_OUT_OF_MEMORY, "could not allocate a launch context");
   // fixed-point colour accumulators and sample counters for requests with
@@ -390,6 +391,8 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   for (pr_scene* s : scenes) user = user || (s->n_types_present >> PR_USER_TYPE_BASE) != 0;
   if (user) compact = 0;
   q.compact_pct = (uint32_t)compact;
+  q.track = track_dev;
+  q.done_recs = done_host;
   for (pr_scene* s : scenes) shared = shared && s == scenes[0];
   if (shared) {
     // one scene for the whole launch: every workgroup stages its top BVH
@@ -547,7 +550,7 @@ pr_status pr_render(pr_scene* s, const pr_camera* cam, const pr_render_opts* opt
     if (st != PR_OK) return st;
     std::lock_guard<std::mutex> lk(s->mu);
     st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), compact_for(s, opts, 0), false, nullptr,
-                         (hipStream_t)stream, nullptr);
+                         (hipStream_t)stream, nullptr, nullptr, nullptr);
     return st == PR_OK ? ok() : st;
   } catch (...) {
     return set_error(PR_ERR_DEVICE, "unexpected exception");
@@ -589,7 +592,7 @@ pr_status pr_render_counts(pr_scene* s, const pr_camera* cam, const pr_render_op
     {
       std::lock_guard<std::mutex> lk(s->mu);
       st = launch_prepared(reqs, scenes, total, budget_for(s, opts, 0), compact_for(s, opts, 0), false, d,
-                           nullptr, nullptr);
+                           nullptr, nullptr, nullptr, nullptr);
     }
     if (st == PR_OK) {
       e = hipDeviceSynchronize();
@@ -626,7 +629,7 @@ pr_status pr_render_batch(const pr_request* rq, uint32_t n, const pr_batch_opts*
     }
     int budget = b.step_budget ? (int)b.step_budget : budget_for(scenes[0], nullptr, 0);
     pr_status st = launch_prepared(reqs, scenes, total, budget, compact_for(scenes[0], nullptr, b.compact_pct),
-                                   b.use_graph != 0, nullptr, (hipStream_t)stream, nullptr);
+                                   b.use_graph != 0, nullptr, (hipStream_t)stream, nullptr, nullptr, nullptr);
     return st == PR_OK ? ok() : st;
   } catch (...) {
     return set_error(PR_ERR_DEVICE, "unexpected exception");

@@ -6,8 +6,11 @@
 // requests in arrival order while their output buffers fit an HBM budget,
 // and launches every admitted request together as one persistent-kernel
 // batch on a free stream -- while earlier batches are still running, so the
-// tail of one batch overlaps the start of the next.  Completion is observed
-// by polling the launch's event from the scheduler thread.
+// tail of one batch overlaps the start of the next.  A request completes
+// when its own pixels are done, not when its launch ends: the kernel counts
+// each request's finished jobs on the device and sets a flag in pinned host
+// memory once they are all done, which the scheduler thread polls (with the
+// request's shadow and bounce ray counts beside it).
 //
 // The scheduler core is independent of HIP: it talks to an Executor, so the
 // same admission, batching and accounting logic also runs against a
@@ -29,7 +32,8 @@
 namespace pr {
 pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_scene*>& scenes,
                           uint32_t total_jobs, int step_budget, int compact, bool use_graph,
-                          unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt);
+                          unsigned long long* counts_dev, hipStream_t stream, hipEvent_t done_evt,
+                          unsigned long long* track_dev, DoneRec* done_host);
 pr_status add_request(std::vector<ReqDev>& reqs, std::vector<pr_scene*>& scenes, pr_scene* s,
                       const pr_camera* cam, const pr_render_opts* o, uint32_t w, uint32_t h, float* rgb,
                       float* t, int32_t* inst, uint32_t tile_w_override, uint32_t& total_jobs,
@@ -106,6 +110,7 @@ struct Ticket {
   unsigned long long* sample_acc = nullptr;
   uint32_t* sample_cnt = nullptr;
   double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+  uint64_t rays_shadow = 0, rays_bounce = 0;
   int state = 0;  // 0 queued, 1 admitted, 2 launched, 3 done
   pr_status status = PR_OK;
   int slot = -1;
@@ -115,28 +120,40 @@ struct Ticket {
 class Executor {
  public:
   virtual ~Executor() = default;
-  virtual pr_status init(uint64_t pool_bytes, uint32_t slots) = 0;
+  virtual pr_status init(uint64_t pool_bytes, uint32_t slots, uint32_t max_batch) = 0;
   virtual char* pool_base() = 0;
   // launch the given admitted tickets on slot; outputs already carved
   virtual pr_status launch(int slot, std::vector<Ticket*>& batch) = 0;
   virtual bool done(int slot) = 0;   // has the slot's last launch completed?
+  // has request i of the slot's running launch completed?  (its ray counts)
+  virtual bool request_done(int slot, size_t i, uint64_t* rays_shadow, uint64_t* rays_bounce) = 0;
   virtual void shutdown() = 0;
 };
 
 class HipExecutor : public Executor {
  public:
   explicit HipExecutor(int dev, bool graph) : dev_(dev), graph_(graph) {}
-  pr_status init(uint64_t pool_bytes, uint32_t slots) override {
+  pr_status init(uint64_t pool_bytes, uint32_t slots, uint32_t max_batch) override {
     hipError_t e = hipSetDevice(dev_);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((e = hipMalloc((void**)&pool_, pool_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(pool)");
+    max_batch_ = max_batch;
     streams_.resize(slots);
     events_.resize(slots);
+    track_.assign(slots, nullptr);
+    done_.assign(slots, nullptr);
     for (uint32_t i = 0; i < slots; ++i) {
       if ((e = hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreate");
       if ((e = hipEventCreateWithFlags(&events_[i], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
+      // per slot: device job and ray counters, host-visible completion records
+      if ((e = hipMalloc((void**)&track_[i], (size_t)max_batch * 3 * sizeof(unsigned long long))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(request counters)");
+      if ((e = hipHostMalloc((void**)&done_[i], (size_t)max_batch * sizeof(DoneRec), hipHostMallocDefault)) !=
+          hipSuccess)
+        return hip_fail(e, "hipHostMalloc(completion records)");
+      std::memset(done_[i], 0, (size_t)max_batch * sizeof(DoneRec));
     }
     return PR_OK;
   }
@@ -162,17 +179,35 @@ class HipExecutor : public Executor {
         reqs.back().sample_cnt = t->sample_cnt;
       }
     }
+    // the slot's previous launch has completed: reset its records and counters
+    const size_t n = batch.size();
+    for (size_t i = 0; i < n; ++i) __atomic_store_n(&done_[slot][i].done, 0u, __ATOMIC_RELAXED);
+    hipError_t e = hipMemsetAsync(track_[slot], 0, n * 3 * sizeof(unsigned long long), streams_[slot]);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(request counters)");
     int budget = budget_for(scenes[0], nullptr, 0);
     return launch_prepared(reqs, scenes, total, budget, compact_for(scenes[0], nullptr, 0), graph_, nullptr,
-                           streams_[slot], events_[slot]);
+                           streams_[slot], events_[slot], track_[slot], done_[slot]);
   }
   bool done(int slot) override { return hipEventQuery(events_[slot]) != hipErrorNotReady; }
+  bool request_done(int slot, size_t i, uint64_t* sh, uint64_t* bo) override {
+    const DoneRec& r = done_[slot][i];
+    if (__atomic_load_n(&r.done, __ATOMIC_ACQUIRE) == 0u) return false;
+    *sh = r.rays_shadow;
+    *bo = r.rays_bounce;
+    return true;
+  }
   void shutdown() override {
     for (auto s : streams_) (void)hipStreamSynchronize(s);
     for (auto e : events_) (void)hipEventDestroy(e);
     for (auto s : streams_) (void)hipStreamDestroy(s);
+    for (auto t : track_)
+      if (t) (void)hipFree(t);
+    for (auto d : done_)
+      if (d) (void)hipHostFree(d);
     streams_.clear();
     events_.clear();
+    track_.clear();
+    done_.clear();
     if (pool_) (void)hipFree(pool_);
     pool_ = nullptr;
   }
@@ -181,8 +216,11 @@ class HipExecutor : public Executor {
   int dev_;
   bool graph_;
   char* pool_ = nullptr;
+  uint32_t max_batch_ = 0;
   std::vector<hipStream_t> streams_;
   std::vector<hipEvent_t> events_;
+  std::vector<unsigned long long*> track_;
+  std::vector<DoneRec*> done_;
 };
 
 // Simulated device: a launch completes after a time proportional to the
@@ -190,7 +228,7 @@ class HipExecutor : public Executor {
 class SimExecutor : public Executor {
  public:
   explicit SimExecutor(uint32_t us_per_mpix) : us_per_mpix_(us_per_mpix) {}
-  pr_status init(uint64_t, uint32_t slots) override {
+  pr_status init(uint64_t, uint32_t slots, uint32_t) override {
     busy_until_.assign(slots, 0.0);
     return PR_OK;
   }
@@ -202,6 +240,8 @@ class SimExecutor : public Executor {
     return PR_OK;
   }
   bool done(int slot) override { return now_s() >= busy_until_[slot]; }
+  // a simulated launch completes all its requests together
+  bool request_done(int, size_t, uint64_t*, uint64_t*) override { return false; }
   void shutdown() override {}
 
  private:
@@ -220,7 +260,11 @@ struct pr_server {
   std::condition_variable cv_sched, cv_done;
   std::deque<Ticket*> waiting;                     // FIFO, not yet admitted
   std::vector<Ticket*> admitted;                   // carved, not yet launched
-  std::vector<std::vector<Ticket*>> slot_batch;    // per slot: tickets of its running launch
+  // per slot: tickets of its running launch, by request index; an entry is
+  // cleared once that request has completed (it may then be released while
+  // the launch still runs)
+  std::vector<std::vector<Ticket*>> slot_batch;
+  std::vector<bool> slot_busy;
   std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -249,22 +293,45 @@ struct pr_server {
     }
   }
 
+  void finish(Ticket* tk, double t) {
+    tk->t_done = t;
+    tk->state = 3;
+    ++stats.completed;
+  }
+
   void loop() {
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
       bool progressed = false;
-      // 1. completions
+      // 1. completions: requests whose device flag is set, then whole launches
       for (size_t s = 0; s < slot_batch.size(); ++s) {
-        if (slot_batch[s].empty() || !exec->done((int)s)) continue;
-        double t = now_s();
-        for (Ticket* tk : slot_batch[s]) {
-          tk->t_done = t;
-          tk->state = 3;
-          ++stats.completed;
+        if (!slot_busy[s]) continue;
+        bool any = false;
+        for (size_t i = 0; i < slot_batch[s].size(); ++i) {
+          Ticket* tk = slot_batch[s][i];
+          if (tk && exec->request_done((int)s, i, &tk->rays_shadow, &tk->rays_bounce)) {
+            finish(tk, now_s());
+            slot_batch[s][i] = nullptr;
+            any = true;
+          }
         }
-        slot_batch[s].clear();
-        progressed = true;
-        cv_done.notify_all();
+        if (exec->done((int)s)) {
+          const double t = now_s();
+          for (size_t i = 0; i < slot_batch[s].size(); ++i) {
+            Ticket* tk = slot_batch[s][i];
+            if (!tk) continue;
+            // the launch has ended: its records are final
+            (void)exec->request_done((int)s, i, &tk->rays_shadow, &tk->rays_bounce);
+            finish(tk, t);
+          }
+          slot_batch[s].clear();
+          slot_busy[s] = false;
+          any = true;
+        }
+        if (any) {
+          progressed = true;
+          cv_done.notify_all();
+        }
       }
       // 2. admission: FIFO while the head fits the pool (no skipping: no starvation)
       while (!waiting.empty()) {
@@ -286,7 +353,7 @@ struct pr_server {
       while (!admitted.empty()) {
         int free_slot = -1;
         for (size_t s = 0; s < slot_batch.size(); ++s)
-          if (slot_batch[s].empty()) {
+          if (!slot_busy[s]) {
             free_slot = (int)s;
             break;
           }
@@ -294,6 +361,13 @@ struct pr_server {
         size_t n = std::min<size_t>(admitted.size(), opts.max_batch);
         std::vector<Ticket*> batch(admitted.begin(), admitted.begin() + n);
         admitted.erase(admitted.begin(), admitted.begin() + n);
+        // smallest first within the launch: the job queue hands out requests
+        // in table order, and each request completes on its own, so the small
+        // ones finish early instead of behind a large one
+        std::stable_sort(batch.begin(), batch.end(), [](const Ticket* a, const Ticket* b) {
+          return (uint64_t)a->req.width * a->req.height * a->req.opts.spp <
+                 (uint64_t)b->req.width * b->req.height * b->req.opts.spp;
+        });
         double t = now_s();
         pr_status st = exec->launch(free_slot, batch);
         ++stats.launches;
@@ -309,12 +383,16 @@ struct pr_server {
             tk->state = 2;
           }
         }
-        if (st == PR_OK) slot_batch[free_slot] = batch;
-        else cv_done.notify_all();
+        if (st == PR_OK) {
+          slot_batch[free_slot] = batch;
+          slot_busy[free_slot] = true;
+        } else {
+          cv_done.notify_all();
+        }
         progressed = true;
       }
       bool inflight = false;
-      for (auto& b : slot_batch) inflight |= !b.empty();
+      for (size_t s = 0; s < slot_busy.size(); ++s) inflight = inflight || slot_busy[s];
       if (stop && waiting.empty() && admitted.empty() && !inflight) break;
       if (!progressed) {
         // poll running launches every 20 us; sleep until a submit otherwise
@@ -337,7 +415,7 @@ pr_status create_server(const pr_server_opts* o, std::unique_ptr<Executor> exec,
   auto* s = new pr_server();
   s->opts = *o;
   s->exec = std::move(exec);
-  pr_status st = s->exec->init(o->hbm_budget_bytes, o->max_inflight);
+  pr_status st = s->exec->init(o->hbm_budget_bytes, o->max_inflight, o->max_batch);
   if (st != PR_OK) {
     s->exec->shutdown();
     delete s;
@@ -345,6 +423,7 @@ pr_status create_server(const pr_server_opts* o, std::unique_ptr<Executor> exec,
   }
   s->pool = std::make_unique<PoolAlloc>(o->hbm_budget_bytes);
   s->slot_batch.resize(o->max_inflight);
+  s->slot_busy.assign(o->max_inflight, false);
   s->thread = std::thread([s] { s->loop(); });
   *out = s;
   return ok();
@@ -448,6 +527,8 @@ pr_status pr_server_wait(pr_server* srv, uint64_t ticket, uint32_t timeout_ms, p
   out->t_launch = t->t_launch;
   out->t_done = t->t_done;
   out->rays_primary = (uint64_t)t->req.width * t->req.height * t->req.opts.spp;
+  out->rays_shadow = t->rays_shadow;
+  out->rays_bounce = t->rays_bounce;
   out->user_tag = t->req.user_tag;
   if (t->status != PR_OK) return set_error(t->status, "request failed");
   return ok();

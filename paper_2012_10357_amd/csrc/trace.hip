@@ -248,6 +248,9 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   uint32_t cur_type = 0;
   float t = 0.f;
   uint32_t job_evals = 0;   // estimator evaluations of the current pixel job
+  // tracked launches: finished jobs and rays begun for request rc_req, not
+  // yet added to the request's device counters
+  uint32_t rc_req = 0, rc_jobs = 0, rc_sh = 0, rc_bo = 0;
   uint32_t march_steps = 0; // steps of the current march already counted in job_evals
   int help_owner = -1;      // K_HSHADOW: lane whose primary hit this shadow ray serves
   bool donated = false;     // this lane's primary shadow ray was handed off
@@ -330,6 +333,9 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     stack_mem[sp++][tid] = 0;
     mode = M_TRAVERSE;
     if constexpr (COUNT) atomicAdd(&cnt_lds[28 + (k == K_HSHADOW ? K_SHADOW : k)], 1ull);
+    // a handed-off shadow ray is counted by the lane that posted it
+    rc_sh += (k == K_SHADOW || k == K_BSHADOW) ? 1u : 0u;
+    rc_bo += k == K_BOUNCE ? 1u : 0u;
   };
 
   auto primary_ray = [&]() __attribute__((always_inline)) {
@@ -400,6 +406,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         atomicExch(&R->sample_cnt[pix], 0u);
       }
     }
+    ++rc_jobs;
     has_job = false;
     mode = M_IDLE;
   };
@@ -431,6 +438,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       if (reqs[m].job_begin <= j) a = m; else b = m;
     }
     bind_request(a);
+    rc_req = a;   // this lane's counts were flushed while it was idle
     uint32_t local = j - R->job_begin;
     const uint32_t per_tile = 64u * spp;
     const uint32_t q = local / per_tile, rem = local - q * per_tile;
@@ -442,6 +450,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     py = (int)(ty * th + li / tw);
     if (px >= (int)R->width || py >= (int)R->height) {
       // ragged tile edge: nothing to render
+      ++rc_jobs;
       has_job = false;
       mode = M_IDLE;
       return;
@@ -664,6 +673,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       tk_state[wv][lane] = T_POSTED;
       donated = true;
+      ++rc_sh;
       start_bounce();
       return;
     }
@@ -951,6 +961,54 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   };
 
+  // Tracked launches: lanes with finished jobs add them, with the rays they
+  // began, to their request's device counters -- summed over the wave per
+  // request, one atomic each.  All of the wave's pixel stores are made
+  // visible first, and the ray counts are added before the job count, so the
+  // wave whose add completes a request's job count sees every pixel and ray
+  // of it: it copies the ray totals into the request's host-visible record
+  // and sets its done flag (system scope).  all: every lane flushes (at the
+  // end); otherwise the lanes that have finished jobs to report (their
+  // counts belong to rc_req however the lane is occupied now: a lane helping
+  // another with its shadow ray begins no counted ray).
+  unsigned long long* const track = queue->track;
+  DoneRec* const done_recs = queue->done_recs;
+  auto flush_counts = [&](bool all) __attribute__((always_inline)) {
+    const bool fl = rc_jobs != 0u || (all && (rc_sh | rc_bo) != 0u);
+    unsigned long long m = __ballot(fl);
+    if (m == 0ull) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    while (m != 0ull) {
+      const int leader = __ffsll((long long)m) - 1;
+      const uint32_t r = (uint32_t)__shfl((int)rc_req, leader);
+      const bool sel = fl && rc_req == r;
+      uint32_t j = sel ? rc_jobs : 0u, a = sel ? rc_sh : 0u, b = sel ? rc_bo : 0u;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        j += (uint32_t)__shfl_xor((int)j, d);
+        a += (uint32_t)__shfl_xor((int)a, d);
+        b += (uint32_t)__shfl_xor((int)b, d);
+      }
+      if (lane == leader) {
+        const ReqDev* Rr = r < kLdsReqs ? &lds_reqs[r] : reqs + r;
+        const unsigned long long total = (unsigned long long)(Rr->job_end - Rr->job_begin);
+        unsigned long long* tr = track + 3 * (size_t)r;
+        if (a) atomicAdd(tr + 1, (unsigned long long)a);
+        if (b) atomicAdd(tr + 2, (unsigned long long)b);
+        const unsigned long long before =
+            __hip_atomic_fetch_add(tr, (unsigned long long)j, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + j == total) {
+          DoneRec* dr = done_recs + r;
+          dr->rays_shadow = __hip_atomic_load(tr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          dr->rays_bounce = __hip_atomic_load(tr + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&dr->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      if (sel) rc_jobs = rc_sh = rc_bo = 0u;
+      m &= ~__ballot(sel);
+    }
+  };
+
   // ---------------- main loop
   if constexpr (POOL) {
     if (tid < kTypeKeys * 8) pend[tid >> 3][tid & 7] = 0u;
@@ -986,6 +1044,8 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
+    // finished jobs are counted before any lane starts a new one
+    if (track) flush_counts(false);
     // Refill idle lanes.  Each wave holds a reservation of consecutive job
     // indices [res_cur, res_end) and takes a fresh chunk of kChunk jobs with
     // one atomic only when the reservation cannot serve all idle lanes; jobs
@@ -1149,6 +1209,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   }
 
+  if (track) flush_counts(true);
   if constexpr (COUNT) {
     atomicAdd(&cnt_lds[32], c_nodes);
     atomicAdd(&cnt_lds[33], c_clips);

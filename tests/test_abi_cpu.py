@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(P):
     L = C.CDLL(P.LIB_PATH)
     for name in declared:
         assert hasattr(L, name), name
-    assert P.abi_version() == P.PR_ABI_VERSION == 7
+    assert P.abi_version() == P.PR_ABI_VERSION == 8
     assert P.device_count() >= 0
 
 

@@ -150,6 +150,7 @@ def test_server_mix_equals_alone():
             r.camera = W.camera((1.0 * (i % 3), 1.5, -6.0))
             r.opts.bounces = 1
         tickets.append(srv.submit(dev[r.scene_index], r.camera, r.opts, tag=i))
+    import torch
     for tk, r in zip(tickets, reqs):
         res = srv.wait(tk, 60000)
         H, Wd = res.height, res.width
@@ -157,6 +158,11 @@ def test_server_mix_equals_alone():
                d2h(res.inst, (H, Wd), np.int32))
         _eq(got, gpu_render(P, dev[r.scene_index], r.camera, r.opts))
         assert res.t_submit <= res.t_admit <= res.t_launch <= res.t_done
+        # the ray counts the device reported for this request in the mix
+        c = P.render_counts(dev[r.scene_index], r.camera, r.opts,
+                            torch.empty((H, Wd, 3), dtype=torch.float32, device="cuda"))
+        assert res.rays_primary == int(c[28])
+        assert (res.rays_shadow, res.rays_bounce) == (int(c[29] + c[31]), int(c[30]))
         srv.release(tk)
     st = srv.stats()
     assert st.completed == 24 and st.pool_bytes_in_use == 0
@@ -252,3 +258,42 @@ def test_regrouping_invariance(case):
     c_pool = P.render_counts(sc, cam, opts, rgb, compact=100)
     assert np.array_equal(c_plain, c_pool), (c_plain, c_pool)
     sc.close()
+
+
+def test_server_requests_complete_on_their_own():
+    """Requests launched together complete when their own pixels are done
+    (device flag), smallest first: small requests batched with a large one
+    are done, correct and releasable before the large one finishes."""
+    P = require_gpu()
+    desc = W.random_instances_scene(np.random.default_rng(6), 1500, W.C5_KINDS)
+    sc = P.Scene(desc)
+    srv = P.Server(2 << 30, max_inflight=1, max_batch=16)
+    srv.add_scene(sc)
+    cam = W.camera((0.0, 8.0, -55.0))
+    big = W.RenderOpts(2048, 2048, spp=4, jitter=1, seed=1, max_steps=256, tmax=200.0)
+    small = [W.RenderOpts(64 + 16 * i, 48, spp=1 + i % 3, jitter=1, seed=10 + i, max_steps=256, tmax=200.0)
+             for i in range(6)]
+    # a first request keeps the single slot busy while the rest queue up, so
+    # the large request and the small ones are launched together
+    first = srv.submit(sc, cam, W.RenderOpts(1024, 1024, spp=2, jitter=1, seed=2, max_steps=256, tmax=200.0))
+    t_big = srv.submit(sc, cam, big)
+    t_small = [srv.submit(sc, cam, o, tag=i) for i, o in enumerate(small)]
+    srv.wait(first, 120000)
+    srv.release(first)
+    done_small = []
+    for tk, o in zip(t_small, small):
+        res = srv.wait(tk, 120000)
+        got = (d2h(res.rgb, (o.height, o.width, 3), np.float32), d2h(res.t, (o.height, o.width), np.float32),
+               d2h(res.inst, (o.height, o.width), np.int32))
+        done_small.append((res.t_launch, res.t_done))
+        srv.release(tk)       # while the large request may still be rendering
+        _eq(got, gpu_render(P, sc, cam, o))
+    rb = srv.wait(t_big, 120000)
+    srv.release(t_big)
+    st = srv.stats()
+    srv.close()
+    assert st.launches == 2, st.launches
+    assert all(tl == rb.t_launch for tl, _ in done_small)
+    assert max(td for _, td in done_small) < rb.t_done
+    print("small done after launch (ms):", [round((td - tl) * 1e3, 2) for tl, td in done_small],
+          "large:", round((rb.t_done - rb.t_launch) * 1e3, 2), flush=True)
