@@ -1,7 +1,8 @@
 """Benchmark: Mrays/s on the 1920x1080 four-primitive teaser scene on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-batch] [--no-served] [--served-seconds S]
+                    [--no-batch] [--no-served] [--no-c3] [--no-next] [--served-seconds S]
+                    [--only c3|c4] [--compact N]
 
 One step = one full frame of the teaser workload: 1920x1080, 1 sample per
 pixel, two pac-men + quaternion Julia + power-8 Mandelbulb, 256 march steps,
@@ -15,11 +16,13 @@ FP32 work of the tracing kernel -- estimator evaluations and fractal
 iterations counted per launch times a fixed per-evaluation flop table
 (below) -- over its average duration measured with HIP events on the launch
 stream; ``cpu_baseline`` times the FP64 oracle on a bounded pixel sample.
-Optional sub-objects time the batched form (64 requests in one persistent
-launch vs 64 plain launches), the served form (Poisson arrivals), and the
-next-step workloads: the sample scene with its triangle plane, the cut Julia
-set, the Mandelbulb animation, and the teaser with its pac-men as a user hit
-group.
+Sub-objects time C3 (1024 instances, 4 spp) and the batched form (64 requests
+in one persistent launch vs 64 plain launches), each with its own roofline;
+the served form (a 2 s warm-up, then a 30 s open-loop Poisson trace at
+200 req/s and at 100 req/s, server vs FIFO plain launches); and the next-step
+workloads: the sample scene with its triangle plane, the cut Julia set, the
+Mandelbulb animation, and the teaser with its pac-men as a user hit group.
+``--only c3|c4`` times just that workload (for profiling).
 """
 from __future__ import annotations
 
@@ -171,22 +174,24 @@ def committed_traffic():
     return committed_counters().get("traffic_bytes_per_launch")
 
 
-def bench_batched(P, W, torch, dev):
+def bench_batched(P, W, torch, dev, reps=5, compare=True):
     """64 requests over the teaser scene: one persistent launch (graph-captured,
-    autotuned) vs one plain pr_render launch per request, same stream."""
+    autotuned) vs one plain pr_render launch per request, same stream.
+    compare=False times the batched launch alone, with the tuned-or-default
+    launch settings and no autotuning (for profiling)."""
     wl = W.c4()
     sc = P.Scene(wl.scenes[0])
     outs = [torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev)
             for r in wl.requests]
-    rays = 0
+    rays, flops = 0, 0.0
     for r, o in zip(wl.requests, outs):
         c = P.render_counts(sc, r.camera, r.opts, o)
         rays += int(c[28:32].sum())
+        flops += algorithmic_flops(c)
     reqs = P.make_requests([(sc, r.camera, r.opts, o, None, None, i)
                             for i, (r, o) in enumerate(zip(wl.requests, outs))])
-    best = P.autotune(reqs)
+    best = P.autotune(reqs) if compare else P.BatchOpts(0, 0, 0, 0, 0)
     stream = torch.cuda.Stream(device=dev)
-    reps = 5
 
     def run(fn):
         with torch.cuda.stream(stream):
@@ -204,15 +209,27 @@ def bench_batched(P, W, torch, dev):
 
     def batched():
         P.render_batch(reqs, tile=(best.tile_w, best.tile_h), step_budget=best.step_budget,
-                       use_graph=True, stream=stream)
+                       use_graph=True, stream=stream, compact=best.compact_pct)
 
-    t_plain, t_batch = run(plain), run(batched)
+    t_plain = run(plain) if compare else float("nan")
+    t_batch = run(batched)
+    # kernel time of the batched launch alone (HIP events on its stream)
+    with torch.cuda.stream(stream):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            batched()
+        b.record(stream)
+    torch.cuda.synchronize()
+    k_ms = a.elapsed_time(b) / reps
     sc.close()
     return {"requests": len(wl.requests), "rays_per_batch": rays,
+            "roofline": roofline_of(flops, k_ms, "trace_kernel (one persistent launch, graph replay)"),
             "batched_mrays_s": round(rays / t_batch / 1e6, 2), "batched_ms": round(t_batch * 1e3, 3),
             "plain_mrays_s": round(rays / t_plain / 1e6, 2), "plain_ms": round(t_plain * 1e3, 3),
             "speedup": round(t_plain / t_batch, 3),
-            "tuned": {"tile": [best.tile_w, best.tile_h], "step_budget": best.step_budget}}
+            "tuned": {"tile": [best.tile_w, best.tile_h], "step_budget": best.step_budget,
+                      "compact_pct": best.compact_pct}}
 
 
 def _frame_rate(P, torch, dev, sc, cam, opts, reps=5):
@@ -323,19 +340,26 @@ def bench_f3(P, W, torch, dev):
             "builtin_ms": builtin["ms"], "builtin_rays": builtin["rays"], "first_build_s": round(build_s, 1)}
 
 
-def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
-    """Open-loop Poisson trace (200 req/s by default) over 8 resident scenes:
-    the continuous-batching server vs FIFO per-request pr_render launches."""
+def bench_served(P, W, torch, dev, seconds, rate_hz=200.0, warmup_s=2.0):
+    """Open-loop Poisson trace over 8 resident scenes (256..4096 instances,
+    sides 256..2048, 1..4 spp): requests arrive for warmup_s + seconds; those
+    arriving in the first warmup_s are served but not measured.  The
+    continuous-batching server against FIFO per-request pr_render launches on
+    the same arrival trace.  Latency = completion (the device flag seen by the
+    host for the server; the stream synchronised for FIFO) minus the scheduled
+    arrival; throughput = rays of the measured requests over the window from
+    the first measured arrival to the last measured completion."""
     import threading
     scenes = [P.Scene(s) for s in W.c5_scenes()]
-    n_req = max(20, int(rate_hz * seconds))
+    n_req = max(20, int(rate_hz * (seconds + warmup_s)))
     reqs = W.c5_requests(n_req, rate_hz=rate_hz)
-    prim_rays = sum(r.opts.width * r.opts.height * r.opts.spp for r in reqs)
+    measured = np.array([r.arrival_s >= warmup_s for r in reqs])
+    prim = np.array([r.opts.width * r.opts.height * r.opts.spp for r in reqs], np.float64)
 
     # --- server
     srv = P.Server(16 << 30, max_inflight=4, max_batch=64, use_graph=False)
-    for s in scenes:
-        srv.add_scene(s)
+    for sc_ in scenes:
+        srv.add_scene(sc_)
     tickets = [None] * n_req
     t_base = time.monotonic() + 0.2
     sub_err = []
@@ -353,7 +377,8 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
     th = threading.Thread(target=submitter)
     th.start()
     lat = np.zeros(n_req)
-    done_last = 0.0
+    done = np.zeros(n_req)
+    shadow = np.zeros(n_req)
     for i in range(n_req):
         while tickets[i] is None and th.is_alive():
             time.sleep(0.0005)
@@ -361,21 +386,26 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
             break
         res = srv.wait(tickets[i], 600000)
         lat[i] = res.t_done - (t_base + reqs[i].arrival_s)
-        done_last = max(done_last, res.t_done)
+        done[i] = res.t_done - t_base
+        shadow[i] = res.rays_shadow
         srv.release(tickets[i])
     th.join()
     if sub_err:
         raise sub_err[0]
     stats = srv.stats()
     srv.close()
-    span = done_last - t_base
-    served = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-              "primary_mrays_s": round(prim_rays / span / 1e6, 2), "launches": int(stats.launches)}
+    t0 = min(r.arrival_s for r, m in zip(reqs, measured) if m)
+    span = float(done[measured].max()) - t0
+    served = {"p50_ms": round(float(np.percentile(lat[measured], 50)) * 1e3, 2),
+              "p99_ms": round(float(np.percentile(lat[measured], 99)) * 1e3, 2),
+              "primary_mrays_s": round(prim[measured].sum() / span / 1e6, 2),
+              "primary_shadow_mrays_s": round((prim[measured].sum() + shadow[measured].sum()) / span / 1e6, 2),
+              "launches": int(stats.launches)}
 
     # --- FIFO baseline: one pr_render per request in arrival order, synchronised
     stream = torch.cuda.Stream(device=dev)
     lat_f = np.zeros(n_req)
+    done_f = np.zeros(n_req)
     buf = {}
     t_base = time.monotonic() + 0.2
     with torch.cuda.stream(stream):
@@ -388,15 +418,55 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0):
                 buf[key] = torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev)
             P.render(scenes[r.scene_index], r.camera, r.opts, buf[key], stream=stream)
             stream.synchronize()
-            lat_f[i] = time.monotonic() - (t_base + r.arrival_s)
-    span_f = time.monotonic() - t_base
-    for s in scenes:
-        s.close()
-    fifo = {"p50_ms": round(float(np.percentile(lat_f, 50)) * 1e3, 2),
-            "p99_ms": round(float(np.percentile(lat_f, 99)) * 1e3, 2),
-            "primary_mrays_s": round(prim_rays / span_f / 1e6, 2)}
-    return {"requests": n_req, "rate_hz": rate_hz, "trace_s": round(reqs[-1].arrival_s, 2),
+            done_f[i] = time.monotonic() - t_base
+            lat_f[i] = done_f[i] - r.arrival_s
+    for sc_ in scenes:
+        sc_.close()
+    span_f = float(done_f[measured].max()) - t0
+    fifo = {"p50_ms": round(float(np.percentile(lat_f[measured], 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat_f[measured], 99)) * 1e3, 2),
+            "primary_mrays_s": round(prim[measured].sum() / span_f / 1e6, 2)}
+    return {"requests": n_req, "measured": int(measured.sum()), "rate_hz": rate_hz, "warmup_s": warmup_s,
+            "trace_s": round(reqs[-1].arrival_s, 2), "offered_primary_mrays_s":
+                round(prim[measured].sum() / (reqs[-1].arrival_s - t0) / 1e6, 1),
             "server": served, "fifo_plain": fifo}
+
+
+def roofline_of(flops, kernel_ms, name, **extra):
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "kernel": name, "kernel_ms": round(kernel_ms, 4),
+           "flops_per_launch": flops}
+    out.update(extra)
+    return out
+
+
+def bench_c3(P, W, torch, dev, reps=5, compact=0):
+    """C3: 1080p, 4 jittered samples, 1024 instances of five types, SAH BVH,
+    shadows: rays and algorithmic flops from the instrumented build, kernel
+    time from HIP events around reps launches on the launch stream."""
+    wl = W.c3()
+    sc = P.Scene(wl.scenes[0])
+    r = wl.requests[0]
+    rgb = torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev)
+    counts = P.render_counts(sc, r.camera, r.opts, rgb, compact=compact)
+    rays = ray_breakdown(counts)
+    flops = algorithmic_flops(counts)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        P.render(sc, r.camera, r.opts, rgb, stream=stream, compact=compact)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            P.render(sc, r.camera, r.opts, rgb, stream=stream, compact=compact)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    sc.close()
+    return {"workload": "C3: 1920x1080, 4 spp jittered, 1024 instances (sphere, torus, box-frame, "
+                        "Mandelbulb, Julia), shadows", "ms": round(ms, 3),
+            "mrays_s": round(sum(rays.values()) / ms / 1e3, 1), "rays": rays,
+            "roofline": roofline_of(flops, ms, "trace_kernel")}
 
 
 def main():
@@ -408,9 +478,17 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-next", action="store_true", help="skip the cut / mesh / animation lines")
-    ap.add_argument("--served-seconds", type=float, default=3.0)
+    ap.add_argument("--no-c3", action="store_true", help="skip the C3 (1024-instance, 4 spp) line")
+    ap.add_argument("--served-seconds", type=float, default=30.0,
+                    help="measured length of each open-loop served trace")
+    ap.add_argument("--served-warmup", type=float, default=2.0,
+                    help="arrivals before this (seconds) are served but not measured")
+    ap.add_argument("--only", choices=["c3", "c4"], default=None,
+                    help="time only this workload (for profiling): C3, or the 64-request batch")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--budget", type=int, default=0)
+    ap.add_argument("--compact", type=int, default=0,
+                    help="regrouping threshold (0 = tuned default, 1..100, 1000 = never)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run one plain device copy of 256 MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -433,6 +511,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
         return
+    if args.only == "c3":
+        print(json.dumps({"c3": bench_c3(P, W, torch, dev, reps=args.steps, compact=args.compact)}), flush=True)
+        return
+    if args.only == "c4":
+        print(json.dumps({"batched": bench_batched(P, W, torch, dev, reps=args.steps, compare=False)}),
+              flush=True)
+        return
     wl = W.c2()
     scene_desc, req = wl.scenes[0], wl.requests[0]
     Wd, H = req.opts.width, req.opts.height
@@ -441,7 +526,8 @@ def main():
     tile = (args.tile, 64 // args.tile) if args.tile else (0, 0)
 
     # work counts of this frame (instrumented build, untimed)
-    counts = P.render_counts(sc, req.camera, req.opts, rgb, tile=tile, step_budget=args.budget)
+    counts = P.render_counts(sc, req.camera, req.opts, rgb, tile=tile, step_budget=args.budget,
+                             compact=args.compact)
     rays = ray_breakdown(counts)
     rays_per_frame = sum(rays.values())
     flops_per_frame = algorithmic_flops(counts)
@@ -451,12 +537,14 @@ def main():
           for _ in range(args.steps)]
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget)
+            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget,
+                     compact=args.compact)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
             ev[i][0].record(stream)
-            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget)
+            P.render(sc, req.camera, req.opts, rgb, stream=stream, tile=tile, step_budget=args.budget,
+                     compact=args.compact)
             ev[i][1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -490,15 +578,19 @@ def main():
     out["roofline"]["valu_issue_frac"] = counters.get("valu_issue_utilisation")
     out["roofline"]["active_lane_frac"] = counters.get("active_lane_fraction")
     sc.close()
+    if not args.no_c3:
+        out["c3"] = bench_c3(P, W, torch, dev, compact=args.compact)
+        print(f"# c3: {out['c3']}", file=sys.stderr, flush=True)
     if not args.no_batch:
         out["batched"] = bench_batched(P, W, torch, dev)
         print(f"# batched: {out['batched']}", file=sys.stderr, flush=True)
     if not args.no_served:
-        out["served"] = bench_served(P, W, torch, dev, args.served_seconds)
+        out["served"] = bench_served(P, W, torch, dev, args.served_seconds, warmup_s=args.served_warmup)
         print(f"# served: {out['served']}", file=sys.stderr, flush=True)
         # the same requests at half the rate, below the GPU's capacity: the
         # latency of batching and execution rather than of a growing queue
-        out["served_100hz"] = bench_served(P, W, torch, dev, args.served_seconds, rate_hz=100.0)
+        out["served_100hz"] = bench_served(P, W, torch, dev, args.served_seconds, rate_hz=100.0,
+                                           warmup_s=args.served_warmup)
         print(f"# served at 100 req/s: {out['served_100hz']}", file=sys.stderr, flush=True)
     if not args.no_next:
         out["next"] = bench_next(P, W, torch, dev)

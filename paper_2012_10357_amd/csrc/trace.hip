@@ -430,15 +430,19 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     spp = R->spp;
   };
 
-  auto start_job = [&](uint32_t j) __attribute__((always_inline)) {
-    // locate the request (few requests: linear; many: binary search)
+  // the request a global job index belongs to (binary search)
+  auto request_of = [&](uint32_t j) __attribute__((always_inline)) -> uint32_t {
     uint32_t a = 0, b = n_req;
     while (b - a > 1) {
       uint32_t m = (a + b) >> 1;
       if (reqs[m].job_begin <= j) a = m; else b = m;
     }
+    return a;
+  };
+
+  auto start_job = [&](uint32_t j, uint32_t a) __attribute__((always_inline)) {
     bind_request(a);
-    rc_req = a;   // this lane's counts were flushed while it was idle
+    rc_req = a;   // counts of another request were flushed before this job
     uint32_t local = j - R->job_begin;
     const uint32_t per_tile = 64u * spp;
     const uint32_t q = local / per_tile, rem = local - q * per_tile;
@@ -961,20 +965,22 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   };
 
-  // Tracked launches: lanes with finished jobs add them, with the rays they
-  // began, to their request's device counters -- summed over the wave per
-  // request, one atomic each.  All of the wave's pixel stores are made
-  // visible first, and the ray counts are added before the job count, so the
-  // wave whose add completes a request's job count sees every pixel and ray
-  // of it: it copies the ray totals into the request's host-visible record
-  // and sets its done flag (system scope).  all: every lane flushes (at the
-  // end); otherwise the lanes that have finished jobs to report (their
-  // counts belong to rc_req however the lane is occupied now: a lane helping
-  // another with its shadow ray begins no counted ray).
+  // Tracked launches: the lanes that want it (want) add their finished jobs,
+  // with the rays they began, to their request's device counters -- summed
+  // over the wave per request, one atomic each.  All of the wave's pixel
+  // stores are made visible first, and the ray counts are added before the
+  // job count, so the wave whose add completes a request's job count sees
+  // every pixel and ray of it: it copies the ray totals into the request's
+  // host-visible record and sets its done flag (system scope).  A lane keeps
+  // counting while it works for one request and flushes only before a job
+  // of another one or when it runs out of jobs, since the fence and the
+  // atomics are costly (the counts belong to rc_req however the lane is
+  // occupied meanwhile: a lane helping another with its shadow ray begins no
+  // counted ray).
   unsigned long long* const track = queue->track;
   DoneRec* const done_recs = queue->done_recs;
-  auto flush_counts = [&](bool all) __attribute__((always_inline)) {
-    const bool fl = rc_jobs != 0u || (all && (rc_sh | rc_bo) != 0u);
+  auto flush_counts = [&](bool want) __attribute__((always_inline)) {
+    const bool fl = want && (rc_jobs | rc_sh | rc_bo) != 0u;
     unsigned long long m = __ballot(fl);
     if (m == 0ull) return;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1044,8 +1050,6 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    // finished jobs are counted before any lane starts a new one
-    if (track) flush_counts(false);
     // Refill idle lanes.  Each wave holds a reservation of consecutive job
     // indices [res_cur, res_end) and takes a fresh chunk of kChunk jobs with
     // one atomic only when the reservation cannot serve all idle lanes; jobs
@@ -1068,12 +1072,19 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         nbase = __shfl(nbase, leader);
         seen = nbase + take;
       }
+      uint32_t j = ~0u, a = 0;
       if (!has_job && !exhausted) {
         const uint32_t rank =
             (uint32_t)__popcll(need & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-        const uint32_t j = rank < have ? res_cur + rank : nbase + (rank - have);
+        j = rank < have ? res_cur + rank : nbase + (rank - have);
+        if (j < total_jobs) a = request_of(j);
+      }
+      // a lane's counts are added to its request's counters before it starts
+      // a job of another request, or once it runs out of jobs
+      if (track) flush_counts((!has_job && !exhausted) && (j >= total_jobs || a != rc_req));
+      if (!has_job && !exhausted) {
         if (j < total_jobs) {
-          start_job(j);
+          start_job(j, a);
         } else {
           exhausted = true;
         }
