@@ -128,6 +128,8 @@ def _oracle_chunk(pix):
 KERNEL_SOURCES = ["paper_2012_10357_amd/csrc/trace.hip", "paper_2012_10357_amd/csrc/de.h",
                   "paper_2012_10357_amd/csrc/internal.h", "paper_2012_10357_amd/csrc/render.cpp"]
 TRAFFIC_PROFILE = "profiles/trace_kernel_teaser_1080p_pmc.md"
+C3_PROFILE = "profiles/trace_kernel_c3_1080p_4spp_pmc.md"
+C4_PROFILE = "profiles/trace_kernel_c4_batch_64req_pmc.md"
 
 
 def kernel_source_hash() -> str:
@@ -144,11 +146,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_counters():
-    """Machine-readable figures of the committed counter profile (HBM bytes
+def committed_counters(profile=None):
+    """Machine-readable figures of a committed counter profile (HBM bytes
     per launch, VALU issue utilisation, active-lane fraction), if it was taken
-    on the current kernel source (else an empty dict)."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    on the current kernel source (else an empty dict).  Default: the teaser's."""
+    path = os.path.join(ROOT, profile or TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return {}
     fields = {}
@@ -224,7 +226,8 @@ def bench_batched(P, W, torch, dev, reps=5, compare=True):
     k_ms = a.elapsed_time(b) / reps
     sc.close()
     return {"requests": len(wl.requests), "rays_per_batch": rays,
-            "roofline": roofline_of(flops, k_ms, "trace_kernel (one persistent launch, graph replay)"),
+            "roofline": roofline_of(flops, k_ms, "trace_kernel (one persistent launch, graph replay)",
+                                    profile=C4_PROFILE),
             "batched_mrays_s": round(rays / t_batch / 1e6, 2), "batched_ms": round(t_batch * 1e3, 3),
             "plain_mrays_s": round(rays / t_plain / 1e6, 2), "plain_ms": round(t_plain * 1e3, 3),
             "speedup": round(t_plain / t_batch, 3),
@@ -432,11 +435,16 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0, warmup_s=2.0):
             "server": served, "fifo_plain": fifo}
 
 
-def roofline_of(flops, kernel_ms, name, **extra):
+def roofline_of(flops, kernel_ms, name, profile=None, **extra):
+    """FP32 roofline of one launch; HBM traffic, VALU issue utilisation and
+    active-lane fraction from the workload's committed counter profile when
+    it was taken on the current kernel source (else null)."""
     achieved = flops / (kernel_ms * 1e-3) / 1e12
+    c = committed_counters(profile) if profile else {}
     out = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-           "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "kernel": name, "kernel_ms": round(kernel_ms, 4),
-           "flops_per_launch": flops}
+           "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": c.get("traffic_bytes_per_launch"),
+           "kernel": name, "kernel_ms": round(kernel_ms, 4), "flops_per_launch": float(flops),
+           "valu_issue_frac": c.get("valu_issue_utilisation"), "active_lane_frac": c.get("active_lane_fraction")}
     out.update(extra)
     return out
 
@@ -466,7 +474,7 @@ def bench_c3(P, W, torch, dev, reps=5, compact=0):
     return {"workload": "C3: 1920x1080, 4 spp jittered, 1024 instances (sphere, torus, box-frame, "
                         "Mandelbulb, Julia), shadows", "ms": round(ms, 3),
             "mrays_s": round(sum(rays.values()) / ms / 1e3, 1), "rays": rays,
-            "roofline": roofline_of(flops, ms, "trace_kernel")}
+            "roofline": roofline_of(flops, ms, "trace_kernel", profile=C3_PROFILE)}
 
 
 def main():
