@@ -28,10 +28,12 @@ estimators and closest-hit functions a test registers as NumPy functions
 (``de.register_estimator``, ``de.register_closest_hit``: the twins of the
 user hit groups compiled into the kernel).
 
-Parity status per function is stated in the module headers; the quaternion
-Julia estimator at generic c and the Mandelbulb estimator off the polar axis
-are "parity unpinned" beyond the special cases and invariants checked in
-``tests/test_oracle_pins.py``.
+Parity status per function is stated in the module headers and checked in
+``tests/test_oracle_pins.py``: the fractal estimators are pinned by the planes
+in which they reduce to complex recurrences (the Julia set on its real axis
+and the plane of c; the Mandelbulb on its polar axis and its slices through
+it) and, at generic points, by their symmetries and a second, algebraically
+independent form of their maps.
 """
 from .de import de_eval, TYPE_NAMES  # noqa: F401
 from .tracer import prepare, render, camera_rays, lowbias32  # noqa: F401

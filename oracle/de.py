@@ -32,9 +32,12 @@ generic quaternion c by the complex planes span{1, u} that its orbits keep
 (real axis; the plane of (c1, c2) when c3 = 0), by its invariance under
 rotations of the imaginary part and by the 2x2 complex matrix representation
 of the quaternions; the Mandelbulb on its polar axis (real recurrence
-|x|^P + c), by its (P-1)-fold rotational and mirror symmetries and by the
-agreement of its trigonometric and algebraic power maps.  Off-axis Mandelbulb
-points are parity unpinned beyond those invariants.
+|x|^P + c), on the slice y = 0 and its rotated copies at azimuth 2 pi k / 7
+(a folded complex multibrot, the same recurrence written with complex
+powers), by its (P-1)-fold rotational and mirror symmetries and by the
+agreement of its trigonometric and algebraic power maps.  At a generic
+azimuth off those half-planes the Mandelbulb has no closed-form reduction:
+there the symmetries and the algebraic map are its pins.
 """
 from __future__ import annotations
 

@@ -148,6 +148,27 @@ def real_bulb_axis_de(x, c, n_iter, bailout, power=8):
     return 0.5 * math.log(r) * r / dr
 
 
+def folded_multibrot_slice_de(x, z, n_iter, bailout, power=8):
+    """The Mandelbulb on its slice y = 0, as a complex recurrence.
+
+    A point (x, 0, z) has azimuth 0 or pi, so P times its azimuth is a
+    multiple of 2 pi and the power map keeps it in the slice; with
+    w = z + i x its polar angle (from +z) is |arg w|, so the slice map is
+    w <- (Re w + i |Im w|)^P + c with c = z + i x, a folded multibrot.  The
+    derivative and estimator rules are the Mandelbulb's (r = |w|)."""
+    c = complex(z, x)
+    w = c
+    dr = 1.0
+    for _ in range(n_iter):
+        r = abs(w)
+        if r > bailout:
+            break
+        dr = power * r ** (power - 1) * dr + 1.0
+        w = complex(w.real, abs(w.imag)) ** power + c
+    r = abs(w)
+    return 0.5 * math.log(r) * r / dr
+
+
 def quaternion_matrix_julia_de(p, c, n_iter, bailout):
     """Quaternion Julia estimator computed in the 2x2 complex matrix
     representation of the quaternions: a + b i + c j + d k is the matrix

@@ -441,6 +441,117 @@ def test_p9_mandelbulb_symmetries_and_algebraic_form():
     assert np.quantile(np.abs(de_b - de) / sc, 0.5) > 1e-3
 
 
+# P9b: off the polar axis.  The slice y = 0 reduces to a complex recurrence
+# (a folded multibrot, tests/analytic.py), and by the 7-fold rotational
+# symmetry so do the half-planes at azimuth k pi / 7.  Together with the axis,
+# the symmetries and the algebraic map these checks catch plausible mistakes
+# in the spherical power map (planted below on the CPU).
+
+def _bulb_ok(de, ref):
+    # orbits that graze the bailout radius may take one iteration more or
+    # fewer under rounding; they are rare and dropped
+    return np.isfinite(de) & np.isfinite(ref) & (np.abs(de - ref) <= 1e-9 * np.maximum(np.abs(ref), 1e-3))
+
+
+def _bulb_check_slice(de_fn):
+    rng = np.random.default_rng(91)
+    x, z = rng.uniform(-1.25, 1.25, 400), rng.uniform(-1.25, 1.25, 400)
+    ref = np.array([AN.folded_multibrot_slice_de(a, b, 10, 2.0) for a, b in zip(x, z)])
+    ok = 0
+    for k in (0, 1, 3):   # the slice itself and two of its rotated copies
+        a = 2 * math.pi * k / 7
+        p = np.stack([x * math.cos(a), x * math.sin(a), z], 1)
+        ok += _bulb_ok(de_fn(p), ref).sum()
+    return ok >= 3 * 392
+
+
+def _bulb_check_axis(de_fn):
+    xs = np.linspace(-1.3, 1.3, 260)
+    de = de_fn(np.stack([np.zeros_like(xs), np.zeros_like(xs), xs], 1))
+    ref = np.array([AN.real_bulb_axis_de(x, x, 10, 2.0) for x in xs])
+    return _bulb_ok(de, ref).sum() >= 255
+
+
+def _bulb_check_symmetry(de_fn):
+    rng = np.random.default_rng(92)
+    p = rng.uniform(-1.2, 1.2, (600, 3))
+    a = 2 * math.pi / 7
+    rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    de = de_fn(p)
+    return (_bulb_ok(de_fn(p @ rz.T), de).sum() >= 590 and
+            _bulb_ok(de_fn(p * np.array([1, -1, 1])), de).sum() >= 590)
+
+
+def _bulb_check_algebraic(de_fn):
+    rng = np.random.default_rng(93)
+    p = rng.uniform(-1.2, 1.2, (600, 3))
+    return _bulb_ok(de_fn(p), D.de_mandelbulb(p, 8.0, 10, 2.0, algebraic=True)[0]).sum() >= 590
+
+
+_BULB_CHECKS = [_bulb_check_slice, _bulb_check_axis, _bulb_check_symmetry, _bulb_check_algebraic]
+
+
+def _oracle_bulb(p):
+    return D.de_mandelbulb(p, 8.0, 10, 2.0)[0]
+
+
+@pytest.mark.parametrize("check", _BULB_CHECKS)
+def test_p9b_mandelbulb_off_axis(check):
+    assert check(_oracle_bulb), check.__name__
+
+
+def _planted_bulb_maps():
+    def polar(z, r):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(r > 0, np.arccos(np.clip(z[:, 2] / np.where(r > 0, r, 1.0), -1, 1)), 0.0)
+
+    def sph(rp, th, ph):
+        return np.stack([rp * np.sin(th) * np.cos(ph), rp * np.sin(th) * np.sin(ph), rp * np.cos(th)], -1)
+
+    def theta_from_y(z, r, pw):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            th = np.where(r > 0, np.arccos(np.clip(z[:, 1] / np.where(r > 0, r, 1.0), -1, 1)), 0.0)
+        ph = np.arctan2(z[:, 2], z[:, 0])
+        o = sph(r ** pw, pw * th, pw * ph)
+        return o[:, [0, 2, 1]]
+
+    def sin_cos_swapped(z, r, pw):
+        th, ph, rp = polar(z, r), np.arctan2(z[:, 1], z[:, 0]), r ** pw
+        return np.stack([rp * np.cos(pw * th) * np.cos(pw * ph), rp * np.cos(pw * th) * np.sin(pw * ph),
+                         rp * np.sin(pw * th)], -1)
+
+    def azimuth_times_p_minus_1(z, r, pw):
+        return sph(r ** pw, pw * polar(z, r), (pw - 1) * np.arctan2(z[:, 1], z[:, 0]))
+
+    def azimuth_args_swapped(z, r, pw):
+        return sph(r ** pw, pw * polar(z, r), pw * np.arctan2(z[:, 0], z[:, 1]))
+
+    def x_y_swapped(z, r, pw):
+        return sph(r ** pw, pw * polar(z, r), pw * np.arctan2(z[:, 1], z[:, 0]))[:, [1, 0, 2]]
+
+    def pole_flipped(z, r, pw):
+        o = sph(r ** pw, pw * polar(z, r), pw * np.arctan2(z[:, 1], z[:, 0]))
+        return o * np.array([1.0, 1.0, -1.0])
+
+    def polar_angle_halved(z, r, pw):
+        return sph(r ** pw, 0.5 * pw * polar(z, r), pw * np.arctan2(z[:, 1], z[:, 0]))
+
+    return {f.__name__: f for f in (theta_from_y, sin_cos_swapped, azimuth_times_p_minus_1,
+                                    azimuth_args_swapped, x_y_swapped, pole_flipped, polar_angle_halved)}
+
+
+def test_p9b_mandelbulb_checks_reject_planted_mistakes(monkeypatch):
+    """Each planted mistake in the oracle's spherical power map fails at
+    least two of the checks, the slice reduction among them."""
+    for name, wrong_map in _planted_bulb_maps().items():
+        monkeypatch.setattr(D, "_bulb_map_trig", wrong_map)
+        caught = [chk.__name__ for chk in _BULB_CHECKS if not chk(_oracle_bulb)]
+        monkeypatch.undo()
+        assert "_bulb_check_slice" in caught and len(caught) >= 2, (name, caught)
+    # the real map passes all of them again once restored
+    assert all(chk(_oracle_bulb) for chk in _BULB_CHECKS)
+
+
 # ---------------------------------------------------------------- P10 lower bound
 
 @pytest.mark.parametrize("gt,prm", [
