@@ -6,6 +6,7 @@
 // everything its intersection needs, so a lane loads it once per candidate;
 // the material, needed only when a hit is shaded, sits in a separate array.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/procray.h"
@@ -115,8 +116,17 @@ static_assert(sizeof(ReqDev) == 192, "request record");
 // compact_pct > 0 selects the regrouping kernel: a workgroup pools its lanes'
 // march queries, sorted by primitive type, whenever fewer than compact_pct %
 // of its lanes march or one of its waves marches more than one type.
-struct alignas(16) QueueDev {
-  uint32_t next_job;       // popped with atomicAdd
+//
+// Jobs are handed out in chunks of 64 consecutive indices.  Chunk c belongs
+// to partition c mod kQueueParts, and each partition has its own cursor
+// (its chunks in increasing order, counted in jobs past the partition's
+// first-round chunks), 256 bytes from the next, so the queue atomics of the
+// whole chip spread over kQueueParts addresses instead of contending for one.
+// Every wave starts on the chunk numbered like the wave, without an atomic.
+constexpr uint32_t kQueueParts = 8;
+constexpr uint32_t kCursorWords = 64;
+struct alignas(256) QueueDev {
+  uint32_t reserved0;
   uint32_t total_jobs;
   uint32_t n_req;
   uint32_t n_stage_nodes;  // 0 = no staging
@@ -132,8 +142,12 @@ struct alignas(16) QueueDev {
   unsigned long long* track;
   struct DoneRec* done_recs;
   const void* pad3;
+  uint32_t pad_head[44];
+  // partition cursors (zero at launch), popped with atomicAdd
+  uint32_t cursor[kQueueParts][kCursorWords];
 };
-static_assert(sizeof(QueueDev) == 80, "queue header");
+static_assert(offsetof(QueueDev, pad_head) == 80, "queue header fields");
+static_assert(offsetof(QueueDev, cursor) == 256 && sizeof(QueueDev) == 2304, "queue cursors");
 
 // Completion record of one tracked request, in host-visible (pinned) memory:
 // the device writes the request's ray counts and then sets done, once every

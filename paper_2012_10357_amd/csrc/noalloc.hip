@@ -66,15 +66,21 @@ pr_status scratch_for(int dev, unsigned char** out) {
   return PR_OK;
 }
 
+// The fields of a QueueDev before its cursors, as kernel-argument bytes.
+struct QueueHead {
+  uint4 w[5];
+};
+static_assert(sizeof(QueueHead) == offsetof(QueueDev, pad_head), "queue head");
+
 // Writes the launch's queue header and request record into the scratch
-// header (the queue cursor starts at zero) and clears the accumulator and
-// counter words the request uses.
-__global__ void noalloc_setup(QueueDev q, ReqDev r, unsigned char* base, uint64_t zero_words16) {
+// header, sets the queue cursors to zero and clears the accumulator and
+// counter words the request uses (one block of 256 threads at least).
+__global__ void noalloc_setup(QueueHead qh, ReqDev r, unsigned char* base, uint64_t zero_words16) {
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid == 0) {
-    *(QueueDev*)base = q;
-    *(ReqDev*)(base + sizeof(QueueDev)) = r;
-  }
+  if (tid < 5) ((uint4*)base)[tid] = qh.w[tid];
+  if (tid < sizeof(QueueDev::cursor) / 16)
+    ((uint4*)(base + offsetof(QueueDev, cursor)))[tid] = make_uint4(0, 0, 0, 0);
+  if (tid == 0) *(ReqDev*)(base + sizeof(QueueDev)) = r;
   uint4* acc = (uint4*)(base + kAccOffset);
   for (uint64_t i = tid; i < zero_words16; i += (uint64_t)gridDim.x * blockDim.x) acc[i] = make_uint4(0, 0, 0, 0);
 }
@@ -134,7 +140,9 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
 
     std::lock_guard<std::mutex> lk(s->mu);
     const uint32_t setup_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (zero16 + 255) / 256));
-    hipLaunchKernelGGL(noalloc_setup, dim3(setup_blocks), dim3(256), 0, (hipStream_t)stream, q, r, base, zero16);
+    QueueHead qh;
+    std::memcpy(&qh, &q, sizeof qh);
+    hipLaunchKernelGGL(noalloc_setup, dim3(setup_blocks), dim3(256), 0, (hipStream_t)stream, qh, r, base, zero16);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "noalloc_setup launch");
     const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact};
     if (launch_trace((const ReqDev*)(base + sizeof(QueueDev)), (QueueDev*)base, total, 1, cfg, nullptr, stream) != 0)

@@ -314,10 +314,29 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   };
 
   unsigned long long c_nodes = 0, c_clips = 0;
-  uint32_t res_cur = 0, res_end = 0;   // this wave's reservation of job indices (wave-uniform)
-  uint32_t seen = 0;                   // queue position after this wave's last reservation
-  // the last stretch of the queue, about one chunk per wave of the grid
-  const uint32_t tail_jobs = gridDim.x * (uint32_t)kWavesPerBlock * kChunk;
+  // The job queue's partitions (chunk c belongs to partition c mod
+  // kQueueParts; a partition's cursor counts its jobs past the chunks that
+  // start the grid's waves).  A wave starts on chunk number `gwave` of its
+  // home partition gwave mod kQueueParts and moves to the next partition
+  // when its current one runs out.  Reservations are partition-local job
+  // indices; part_job maps them to job indices.
+  const uint32_t n_grid_waves = gridDim.x * (uint32_t)kWavesPerBlock;
+  const uint32_t gwave = blockIdx.x * (uint32_t)kWavesPerBlock + (uint32_t)wv;
+  const uint32_t n_chunks = (total_jobs + kChunk - 1u) / kChunk;
+  auto part_chunks = [](uint32_t p, uint32_t c) -> uint32_t {
+    return c > p ? (c - p + kQueueParts - 1u) / kQueueParts : 0u;   // chunks < c in partition p
+  };
+  uint32_t part = gwave % kQueueParts, part_moves = 0;
+  uint32_t part_size = part_chunks(part, n_chunks) * kChunk;         // the partition's jobs
+  uint32_t part_first = part_chunks(part, n_grid_waves) * kChunk;    // jobs of its first-round chunks
+  auto part_job = [&](uint32_t k) -> uint32_t {
+    return k < part_size ? (((k / kChunk) * kQueueParts + part) * kChunk) + k % kChunk : ~0u;
+  };
+  // this wave's reservation of partition-local job indices (wave-uniform)
+  uint32_t res_cur = (gwave / kQueueParts) * kChunk, res_end = res_cur + kChunk;
+  uint32_t seen = part_first;          // cursor position after this wave's last reservation
+  // the last stretch of a partition, about one chunk per wave of the grid
+  const uint32_t tail_jobs = n_grid_waves * kChunk / kQueueParts;
 
   auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) __attribute__((always_inline)) {
     ray = r;
@@ -1050,25 +1069,28 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    // Refill idle lanes.  Each wave holds a reservation of consecutive job
-    // indices [res_cur, res_end) and takes a fresh chunk of kChunk jobs with
-    // one atomic only when the reservation cannot serve all idle lanes; jobs
-    // are handed out in increasing order, so once a lane draws an index past
-    // the end, every index still reserved is past the end too.
+    // Refill idle lanes.  Each wave holds a reservation of consecutive
+    // indices [res_cur, res_end) of its current partition and takes a fresh
+    // chunk of kChunk jobs with one atomic on the partition's cursor only
+    // when the reservation cannot serve all idle lanes; a partition hands out
+    // its jobs in increasing order, so once a lane draws an index past its
+    // end, every index still reserved there is past the end too, and the
+    // wave moves on to the next partition that has jobs beyond its first
+    // round (after all of them, the wave's lanes are exhausted).
     const unsigned long long need = __ballot(!has_job && !exhausted);
     if (need) {
       const int leader = __ffsll((long long)need) - 1;
       const uint32_t n = (uint32_t)__popcll(need);
       const uint32_t have = res_end - res_cur;
-      // near the end of the queue a wave takes only the jobs it can start
-      // now, so no job waits in a busy wave's reservation while other waves
-      // run dry
-      const uint32_t take = (total_jobs - (seen < total_jobs ? seen : total_jobs)) < tail_jobs
+      // near the end of the partition a wave takes only the jobs it can
+      // start now, so no job waits in a busy wave's reservation while other
+      // waves run dry
+      const uint32_t take = (part_size - (seen < part_size ? seen : part_size)) < tail_jobs
                                 ? n - (have < n ? have : n)
                                 : kChunk;
       uint32_t nbase = 0;
       if (have < n) {
-        if (lane == leader) nbase = atomicAdd(&queue->next_job, take);
+        if (lane == leader) nbase = atomicAdd(&queue->cursor[part][0], take) + part_first;
         nbase = __shfl(nbase, leader);
         seen = nbase + take;
       }
@@ -1076,20 +1098,25 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
       if (!has_job && !exhausted) {
         const uint32_t rank =
             (uint32_t)__popcll(need & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-        j = rank < have ? res_cur + rank : nbase + (rank - have);
+        j = part_job(rank < have ? res_cur + rank : nbase + (rank - have));
         if (j < total_jobs) a = request_of(j);
       }
+      const bool ran_out = __ballot((!has_job && !exhausted) && j >= total_jobs) != 0ull;
       // a lane's counts are added to its request's counters before it starts
-      // a job of another request, or once it runs out of jobs
+      // a job of another request, or once its partition runs out
       if (track) flush_counts((!has_job && !exhausted) && (j >= total_jobs || a != rc_req));
-      if (!has_job && !exhausted) {
-        if (j < total_jobs) {
-          start_job(j, a);
-        } else {
-          exhausted = true;
-        }
-      }
-      if (have < n) {
+      if (!has_job && !exhausted && j < total_jobs) start_job(j, a);
+      if (ran_out) {
+        do {
+          part = (part + 1u) % kQueueParts;
+          ++part_moves;
+          part_size = part_chunks(part, n_chunks) * kChunk;
+          part_first = part_chunks(part, n_grid_waves) * kChunk;
+        } while (part_moves < kQueueParts && part_size <= part_first);
+        if (part_moves >= kQueueParts) exhausted = true;
+        res_cur = res_end = 0;
+        seen = part_first;
+      } else if (have < n) {
         res_cur = nbase + (n - have);
         res_end = nbase + take;
       } else {
