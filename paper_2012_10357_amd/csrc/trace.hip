@@ -17,12 +17,14 @@
 //    march -> normal -> shade -> shadow / bounce -> ...;
 //  - each loop iteration first refills idle lanes from a device job queue
 //    that spans every request of the launch (a wave reserves 64 consecutive
-//    jobs per queue atomic), then runs the divergent control work, then one
-//    pooled FP64 pass over the normal taps the wave's lanes are waiting for,
-//    then a burst of up to `step_budget` lock-step FP32 estimator
-//    evaluations for all marching lanes; the burst ends early once fewer
-//    than an eighth of the busy lanes still march, so finished lanes are
-//    re-used without paying a control phase every few steps;
+//    jobs per atomic on one of eight partition cursors), then runs the
+//    divergent control work, then one pooled FP64 pass over the normal taps
+//    the wave's lanes are waiting for, then a burst of up to `step_budget`
+//    lock-step FP32 estimator evaluations for all marching lanes (four times
+//    that once the queue has no jobs left for the wave); the burst ends
+//    early once fewer than an eighth of the busy lanes still march, so
+//    finished lanes are re-used without paying a control phase every few
+//    steps;
 //  - the shadow ray of a primary hit that also bounces is handed to an idle
 //    lane of the same wave, so it runs beside the bounce chain;
 //  - BVH stacks live in LDS ([depth][lane] layout, conflict-free);
@@ -847,14 +849,14 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   };
 
-  // A burst of up to step_budget lock-step estimator evaluations of the query
+  // A burst of up to `budget` lock-step estimator evaluations of the query
   // in slot q (for lanes with act): v = sigma DE(o' + t d'); hit if v < eps,
   // else t += v; miss once t passes t1 or the step budget is spent, or on a
   // NaN.  The burst ends once fewer than an eighth of end_n queries still
   // march: a control phase costs about four steps, so lanes that have
   // finished wait a few steps rather than forcing one.  The outcome and the
   // steps taken go back to the slot; returns the query's state.
-  auto march_query = [&](bool act, int q, int end_n) __attribute__((always_inline)) -> uint32_t {
+  auto march_query = [&](bool act, int q, int end_n, int budget) __attribute__((always_inline)) -> uint32_t {
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tq = 0.f, t1q = 0.f, sg = 1.f;
     float kp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float2 cl = make_float2(-__builtin_inff(), 0.f);
@@ -885,7 +887,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     int sq = (int)(meta & 0x1fffu);
     uint32_t st = S_CONT;
     const bool qcut = __ballot(act && cl.x != -__builtin_inff()) != 0ull;
-    for (int it = 0; it < step_budget; ++it) {
+    for (int it = 0; it < budget; ++it) {
       if (act && st == S_CONT) {
         const float qx = ox + tq * dx;
         const float qy = oy + tq * dy;
@@ -977,7 +979,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     const bool act = (uint32_t)lane < n_take;
     const int q = act ? (int)(wi * 32u + (uint32_t)__ffs(myw) - 1u) : tid;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint32_t st = march_query(act, q, (int)n_take);
+    const uint32_t st = march_query(act, q, (int)n_take, step_budget);
     if (act && st == S_CONT) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       atomicOr(&pend[k][q >> 5], 1u << (q & 31));
@@ -1242,8 +1244,12 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     if constexpr (POOL) {
       pool_burst();
     } else {
+      // once the queue has nothing left for this wave, no lane waits for a
+      // refill: bursts run four times longer, so the wave's last pixel
+      // chains pass through fewer control phases
       const bool marching = has_job && mode == M_MARCH;
-      if (__ballot(marching)) march_query(marching, tid, __popcll(busy));
+      const int budget = __ballot(!exhausted) == 0ull ? 4 * step_budget : step_budget;
+      if (__ballot(marching)) march_query(marching, tid, __popcll(busy), budget);
     }
   }
 

@@ -3,6 +3,8 @@
 Results must not depend on how work is scheduled: tile shape, step budget,
 BVH build options, batch composition, hipGraph replay or the server's mix
 all give bitwise-identical pixels."""
+import time
+
 import numpy as np
 import pytest
 
@@ -274,8 +276,13 @@ def test_server_requests_complete_on_their_own():
     small = [W.RenderOpts(64 + 16 * i, 48, spp=1 + i % 3, jitter=1, seed=10 + i, max_steps=256, tmax=200.0)
              for i in range(6)]
     # a first request keeps the single slot busy while the rest queue up, so
-    # the large request and the small ones are launched together
-    first = srv.submit(sc, cam, W.RenderOpts(1024, 1024, spp=2, jitter=1, seed=2, max_steps=256, tmax=200.0))
+    # the large request and the small ones are launched together (the rest
+    # are submitted once the first one's launch has started)
+    first = srv.submit(sc, cam, W.RenderOpts(2048, 2048, spp=2, jitter=1, seed=2, max_steps=256, tmax=200.0))
+    t0 = time.monotonic()
+    while srv.stats().launches < 1:
+        assert time.monotonic() - t0 < 30.0, "the first request was never launched"
+        time.sleep(0.0002)
     t_big = srv.submit(sc, cam, big)
     t_small = [srv.submit(sc, cam, o, tag=i) for i, o in enumerate(small)]
     srv.wait(first, 120000)
