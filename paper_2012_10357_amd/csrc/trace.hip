@@ -466,13 +466,22 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     rc_req = a;   // counts of another request were flushed before this job
     uint32_t local = j - R->job_begin;
     const uint32_t per_tile = 64u * spp;
+    // within a tile the samples of a pixel are consecutive jobs, and an 8x8
+    // tile takes its pixels in Z order, so the 64 jobs of a chunk cover an
+    // 8x8, 8x4 or 4x4 block of pixels at 1, 2 or 4 samples: the lanes of a
+    // wave march nearly the same rays
     const uint32_t q = local / per_tile, rem = local - q * per_tile;
-    uint32_t li = rem & 63u;
-    uint32_t tw = R->tile_w, th = 64u / tw;
+    const uint32_t li = rem / spp;
+    const uint32_t tw = R->tile_w, th = 64u / tw;
+    uint32_t lx = li % tw, ly = li / tw;
+    if (tw == 8u) {
+      lx = (li & 1u) | ((li >> 1) & 2u) | ((li >> 2) & 4u);
+      ly = ((li >> 1) & 1u) | ((li >> 2) & 2u) | ((li >> 3) & 4u);
+    }
     uint32_t tx, ty;
     tile_at(R, q, tx, ty);
-    px = (int)(tx * tw + li % tw);
-    py = (int)(ty * th + li / tw);
+    px = (int)(tx * tw + lx);
+    py = (int)(ty * th + ly);
     if (px >= (int)R->width || py >= (int)R->height) {
       // ragged tile edge: nothing to render
       ++rc_jobs;
@@ -482,7 +491,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
     has_job = true;
     job_evals = 0;
-    s = rem >> 6;
+    s = rem - li * spp;
     primary_ray();
   };
 
