@@ -382,12 +382,17 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   };
 
   // A job is one sample.  With several samples per pixel the samples of a
-  // pixel run as separate jobs on any lanes of any workgroup.  Each adds its
-  // colour, in signed 32.32 fixed point, to the pixel's 64-bit accumulators
-  // with device-scope atomics (two's-complement integer sums are exact, so the
-  // mean does not depend on the order the samples finish in), waits until
-  // those adds are performed, then bumps the pixel's sample counter.  The
-  // sample that completes the count takes the sums with atomic exchanges,
+  // pixel are consecutive jobs and mostly run on lanes of one wave, but may
+  // run on any lanes of any workgroup.  A finished sample's colour is turned
+  // into signed 32.32 fixed point and posted to the lane's query slot (the
+  // lane is idle from then on); at the start of the wave's next loop
+  // iteration the wave sums the posted samples of each pixel (two's-
+  // complement integer sums are exact, so nothing depends on which samples
+  // meet where or in what order).  A pixel whose samples are all there
+  // stores its mean at once.  Otherwise the group adds its sums to the
+  // pixel's 64-bit accumulators with device-scope atomics, waits until those
+  // adds are performed, then adds its sample count to the pixel's counter;
+  // the group that completes the count takes the sums with atomic exchanges,
   // which also clear the accumulators for the next launch, and writes the
   // mean.  Colours are bounded by kMaxColour = 2^24 in magnitude (the scene
   // constants are validated on the host and user closest-hit outputs are
@@ -395,41 +400,94 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   // NaN channel adds nothing and is counted instead, in a 7-bit field of the
   // counter word per channel (bits 0-6 count samples); the mean of a channel
   // that saw a NaN is NaN, as in floating point.
+  bool fin_pend = false;   // a finished sample is posted in this lane's slot
   auto finish_sample = [&](float cr, float cg, float cb) __attribute__((always_inline)) {
-    const size_t pix = (size_t)py * R->width + px;
-    float* o = R->out_rgb + pix * 3;
     if (spp == 1) {
+      float* o = R->out_rgb + ((size_t)py * R->width + px) * 3;
       o[0] = cr;
       o[1] = cg;
       o[2] = cb;
     } else {
       constexpr float kFix = 4294967296.0f;  // 2^32
-      unsigned long long* acc = R->sample_acc + pix * 3;
       const bool nr = cr != cr, ng = cg != cg, nb = cb != cb;
-      atomicAdd(acc + 0, (unsigned long long)__float2ll_rn(nr ? 0.f : cr * kFix));
-      atomicAdd(acc + 1, (unsigned long long)__float2ll_rn(ng ? 0.f : cg * kFix));
-      atomicAdd(acc + 2, (unsigned long long)__float2ll_rn(nb ? 0.f : cb * kFix));
-      // vmcnt also counts stores and atomics without return: wait until the
-      // three adds are acknowledged before the counter can reach its total
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      const uint32_t add = 1u + (nr ? 1u << 7 : 0u) + (ng ? 1u << 14 : 0u) + (nb ? 1u << 21 : 0u);
-      const uint32_t before = atomicAdd(&R->sample_cnt[pix], add);
-      if ((before & 127u) == spp - 1) {
-        const uint32_t nan = before + add;
-        const double scale = 1.0 / (4294967296.0 * (double)spp);
-        const double qnan = __builtin_nan("");
-        const double sr = (double)(long long)atomicExch(acc + 0, 0ull) * scale;
-        const double sg = (double)(long long)atomicExch(acc + 1, 0ull) * scale;
-        const double sb = (double)(long long)atomicExch(acc + 2, 0ull) * scale;
-        o[0] = (float)((nan >> 7) & 127u ? qnan : sr);
-        o[1] = (float)((nan >> 14) & 127u ? qnan : sg);
-        o[2] = (float)((nan >> 21) & 127u ? qnan : sb);
-        atomicExch(&R->sample_cnt[pix], 0u);
-      }
+      const uint64_t fr = (uint64_t)__float2ll_rn(nr ? 0.f : cr * kFix);
+      const uint64_t fg = (uint64_t)__float2ll_rn(ng ? 0.f : cg * kFix);
+      const uint64_t fb = (uint64_t)__float2ll_rn(nb ? 0.f : cb * kFix);
+      qs[Q_OX + 0][tid] = __uint_as_float((uint32_t)fr);
+      qs[Q_OX + 1][tid] = __uint_as_float((uint32_t)(fr >> 32));
+      qs[Q_OX + 2][tid] = __uint_as_float((uint32_t)fg);
+      qs[Q_DX + 0][tid] = __uint_as_float((uint32_t)(fg >> 32));
+      qs[Q_DX + 1][tid] = __uint_as_float((uint32_t)fb);
+      qs[Q_DX + 2][tid] = __uint_as_float((uint32_t)(fb >> 32));
+      qs[Q_T][tid] = __uint_as_float(1u + (nr ? 1u << 7 : 0u) + (ng ? 1u << 14 : 0u) + (nb ? 1u << 21 : 0u));
+      fin_pend = true;
     }
     ++rc_jobs;
     has_job = false;
     mode = M_IDLE;
+  };
+
+  // Sums the posted samples of each pixel (see above).  Runs before any lane
+  // is given new work, so each posting lane is still bound to the request
+  // and pixel of its sample.
+  auto commit_samples = [&]() __attribute__((always_inline)) {
+    const unsigned long long pend = __ballot(fin_pend);
+    if (pend == 0ull) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // group the posting lanes by (request, pixel); the lowest lane of a
+    // group leads it
+    const uint32_t pkey = fin_pend ? (uint32_t)py * R->width + (uint32_t)px : 0u;
+    unsigned long long grp = 0ull;
+    for (unsigned long long rest = pend; rest != 0ull;) {
+      const int lead = __ffsll((long long)rest) - 1;
+      const uint32_t kr = (uint32_t)__shfl((int)req_i, lead), kp = (uint32_t)__shfl((int)pkey, lead);
+      const unsigned long long g = __ballot(fin_pend && req_i == kr && pkey == kp);
+      if (lane == lead) grp = g;
+      rest &= ~g;
+    }
+    if (grp != 0ull) {
+      uint64_t sr = 0, sg = 0, sb = 0;
+      uint32_t add = 0;
+      for (unsigned long long m = grp; m != 0ull; m &= m - 1ull) {
+        const int sl = wv * kWave + (__ffsll((long long)m) - 1);
+        sr += (uint64_t)__float_as_uint(qs[Q_OX + 0][sl]) | ((uint64_t)__float_as_uint(qs[Q_OX + 1][sl]) << 32);
+        sg += (uint64_t)__float_as_uint(qs[Q_OX + 2][sl]) | ((uint64_t)__float_as_uint(qs[Q_DX + 0][sl]) << 32);
+        sb += (uint64_t)__float_as_uint(qs[Q_DX + 1][sl]) | ((uint64_t)__float_as_uint(qs[Q_DX + 2][sl]) << 32);
+        add += __float_as_uint(qs[Q_T][sl]);
+      }
+      const size_t pix = (size_t)pkey;
+      float* o = R->out_rgb + pix * 3;
+      uint32_t nan = add;
+      bool done = (add & 127u) == spp;
+      if (!done) {
+        unsigned long long* acc = R->sample_acc + pix * 3;
+        atomicAdd(acc + 0, (unsigned long long)sr);
+        atomicAdd(acc + 1, (unsigned long long)sg);
+        atomicAdd(acc + 2, (unsigned long long)sb);
+        // vmcnt also counts stores and atomics without return: wait until the
+        // three adds are acknowledged before the counter can reach its total
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const uint32_t before = atomicAdd(&R->sample_cnt[pix], add);
+        nan = before + add;
+        done = (nan & 127u) == spp;
+        if (done) {
+          sr = atomicExch(acc + 0, 0ull);
+          sg = atomicExch(acc + 1, 0ull);
+          sb = atomicExch(acc + 2, 0ull);
+          atomicExch(&R->sample_cnt[pix], 0u);
+        }
+      }
+      if (done) {
+        const double scale = 1.0 / (4294967296.0 * (double)spp);
+        const double qnan = __builtin_nan("");
+        o[0] = (float)((nan >> 7) & 127u ? qnan : (double)(long long)sr * scale);
+        o[1] = (float)((nan >> 14) & 127u ? qnan : (double)(long long)sg * scale);
+        o[2] = (float)((nan >> 21) & 127u ? qnan : (double)(long long)sb * scale);
+      }
+    }
+    fin_pend = false;
   };
 
   auto bind_request = [&](uint32_t a) __attribute__((always_inline)) {
@@ -1058,6 +1116,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (has_job && mode == M_WAIT) collect();
+    commit_samples();
     const unsigned long long posted = __ballot(tk_state[wv][lane] == T_POSTED);
     if (posted) {
       const unsigned long long idle = __ballot(!has_job);
@@ -1262,6 +1321,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
   }
 
+  commit_samples();
   if (track) flush_counts(true);
   if constexpr (COUNT) {
     atomicAdd(&cnt_lds[32], c_nodes);
