@@ -598,10 +598,12 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     const float ix = 1.0f / (ray.dx != 0.f ? ray.dx : copysignf(1e-30f, ray.dx));
     const float iy = 1.0f / (ray.dy != 0.f ? ray.dy : copysignf(1e-30f, ray.dy));
     const float iz = 1.0f / (ray.dz != 0.f ? ray.dz : copysignf(1e-30f, ray.dz));
+    // slab distances as one FMA each: (b - o) / d = b (1/d) - o (1/d)
+    const float oxi = -ray.ox * ix, oyi = -ray.oy * iy, ozi = -ray.oz * iz;
     auto box_entry = [&](const float* lo, const float* hi) __attribute__((always_inline)) -> float {
-      float tx0 = (lo[0] - ray.ox) * ix, tx1 = (hi[0] - ray.ox) * ix;
-      float ty0 = (lo[1] - ray.oy) * iy, ty1 = (hi[1] - ray.oy) * iy;
-      float tz0 = (lo[2] - ray.oz) * iz, tz1 = (hi[2] - ray.oz) * iz;
+      float tx0 = fmaf(lo[0], ix, oxi), tx1 = fmaf(hi[0], ix, oxi);
+      float ty0 = fmaf(lo[1], iy, oyi), ty1 = fmaf(hi[1], iy, oyi);
+      float tz0 = fmaf(lo[2], iz, ozi), tz1 = fmaf(hi[2], iz, ozi);
       float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
       float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
       return tn <= tf ? tn : __builtin_inff();
