@@ -148,6 +148,22 @@ def test_spp_jitter_matches_oracle():
     _check(parity.compare(*flat(*g), orc, "c1 5spp jitter"))
 
 
+@pytest.mark.parametrize("spp,wh", [(16, (24, 20)), (64, (16, 12))])
+def test_many_samples_match_oracle(spp, wh):
+    """Up to the maximum of 64 samples per pixel: a 64-job chunk is then one
+    pixel's samples (summed in the wave when they finish together), and a
+    16-sample pixel spans a quarter chunk."""
+    P = require_gpu()
+    scene = W.c1_scene()
+    cam = W.camera((0, 1, -4))
+    opts = W.RenderOpts(wh[0], wh[1], spp=spp, jitter=1, seed=977 + spp, max_steps=128, eps=1e-4,
+                        tmax=100.0, shadows=1)
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, opts)
+    orc = T.render(scene, cam, opts)
+    _check(parity.compare(*flat(*g), orc, f"c1 {spp}spp jitter"))
+
+
 def test_all_types_scene_with_bounce():
     """Every primitive type, non-trivial rotations and scales, shadows and a bounce."""
     P = require_gpu()
