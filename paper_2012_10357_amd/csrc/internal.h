@@ -79,7 +79,7 @@ struct alignas(16) SceneConstsDev {
 static_assert(sizeof(SceneConstsDev) == 64, "scene constants");
 
 // One render request as seen by the kernel.  192 bytes.  A job is one
-// (pixel, sample); jobs of a tile are ordered sample-major: tile, sample, lane.
+// (pixel, sample); jobs are ordered tile, pixel (Z order in 8x8 tiles), sample.
 // The camera arrives as its orthonormal basis and pixel mapping, computed on
 // the host in double.
 struct alignas(16) ReqDev {
