@@ -337,7 +337,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
   // this wave's reservation of partition-local job indices (wave-uniform)
   uint32_t res_cur = (gwave / kQueueParts) * kChunk, res_end = res_cur + kChunk;
   uint32_t seen = part_first;          // cursor position after this wave's last reservation
-  // the last stretch of a partition, about one chunk per wave of the grid
+  // the last stretch of a partition: about one chunk for each wave that starts in it
   const uint32_t tail_jobs = n_grid_waves * kChunk / kQueueParts;
 
   auto begin_ray = [&](const Ray& r, uint32_t k, float t_lo, float t_hi) __attribute__((always_inline)) {
