@@ -40,6 +40,7 @@ struct LaunchCtx {
   hipStream_t graph_stream = nullptr;
   const void* graph_kernel = nullptr;   // the kernel the graph launches (nullptr: built-in)
   int graph_compact = 0;                // regrouping threshold the graph's kernel runs with
+  bool graph_descend = false;           // the graph's kernel is the build for BVHs not all in LDS
 };
 
 LaunchCtx* acquire_ctx(uint32_t n_req);

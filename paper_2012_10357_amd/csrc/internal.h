@@ -171,6 +171,7 @@ struct LaunchCfg {
   int step_budget;   // DE evaluations between refill checks
   int grid_blocks;   // persistent grid size
   int compact_pct;   // 0 = no regrouping (also written to the queue header)
+  bool descend;      // the launch's BVH is not all staged in LDS (kernel choice only)
 };
 
 }  // namespace pr

@@ -144,7 +144,7 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
     std::memcpy(&qh, &q, sizeof qh);
     hipLaunchKernelGGL(noalloc_setup, dim3(setup_blocks), dim3(256), 0, (hipStream_t)stream, qh, r, base, zero16);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "noalloc_setup launch");
-    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact};
+    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact, s->dnodes.size() > kLdsNodes};
     if (launch_trace((const ReqDev*)(base + sizeof(QueueDev)), (QueueDev*)base, total, 1, cfg, nullptr, stream) != 0)
       return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (s->last_use && (e = hipEventRecord(s->last_use, (hipStream_t)stream)) != hipSuccess)

@@ -421,14 +421,17 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     return user ? launch_trace_user(uk, r0, q0, cf, counts, s)
                 : launch_trace(r0, q0, total_jobs, (uint32_t)reqs.size(), cf, counts, s);
   };
-  LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0), compact};
+  // a launch whose BVH is not all staged in LDS runs the kernel build that
+  // descends to near children without the LDS stack (same results)
+  const bool descend = !(shared && scenes[0]->dnodes.size() <= kLdsNodes);
+  LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0), compact, descend};
   hipError_t e;
   bool graphed = false;
   if (use_graph && stream != nullptr && counts_dev == nullptr) {
     const void* kernel_id = user ? uk.plain : nullptr;
     if (!(c->graph && c->graph_bytes == bytes && c->graph_blocks == cfg.grid_blocks &&
           c->graph_budget == step_budget && c->graph_stream == stream && c->graph_kernel == kernel_id &&
-          c->graph_compact == compact)) {
+          c->graph_compact == compact && c->graph_descend == descend)) {
       if (c->graph) {
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
@@ -457,6 +460,7 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
         c->graph_stream = stream;
         c->graph_kernel = kernel_id;
         c->graph_compact = compact;
+        c->graph_descend = descend;
       }
     }
     if (c->graph) {

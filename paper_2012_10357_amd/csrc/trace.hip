@@ -173,7 +173,7 @@ __device__ __forceinline__ float2 cut_line_of(const InstDev& I, const float ol[3
 
 // The whole path for one workgroup; the kernels below wrap it.  POOL selects
 // the regrouping variant (see the burst below).
-template <bool COUNT, bool POOL>
+template <bool COUNT, bool POOL, bool DESCEND>
 __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue,
                                            int step_budget, unsigned long long* __restrict__ counts) {
   __shared__ uint16_t stack_mem[kStackDepth][kBlock];
@@ -617,7 +617,7 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         mode = M_RAYDONE;
         return;
       }
-      const uint32_t e = stack_mem[--sp][tid];
+      uint32_t e = stack_mem[--sp][tid];
       if (e & 0x8000u) {
         // deferred leaf child: read its range from the parent record
         const NodeDev* pn = node_ptr((e & 0x7fffu) >> 1);
@@ -627,24 +627,53 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         leaf_n = (int)(c + n);
         continue;
       }
-      const NodeDev nd = *node_ptr(e);
-      if (COUNT) ++c_nodes;
-      const float t0 = box_entry(nd.lo0, nd.hi0);
-      const float t1c = (nd.n1 != kNoChild) ? box_entry(nd.lo1, nd.hi1) : __builtin_inff();
-      const bool h0 = t0 != __builtin_inff(), h1 = t1c != __builtin_inff();
-      if (!h0 && !h1) continue;
-      // near child first; the far one (if hit) goes on the stack
-      const bool near0 = h0 && (!h1 || t0 <= t1c);
-      if (h0 && h1) {
-        const uint32_t fc = near0 ? nd.c1 : nd.c0, fn = near0 ? nd.n1 : nd.n0;
-        stack_mem[sp++][tid] = (uint16_t)(fn == 0 ? fc : (0x8000u | (e << 1) | (near0 ? 1u : 0u)));
-      }
-      const uint32_t nc = near0 ? nd.c0 : nd.c1, nn = near0 ? nd.n0 : nd.n1;
-      if (nn == 0) {
-        stack_mem[sp++][tid] = (uint16_t)nc;
+      if constexpr (!DESCEND) {
+        const NodeDev nd = *node_ptr(e);
+        if (COUNT) ++c_nodes;
+        const float t0 = box_entry(nd.lo0, nd.hi0);
+        const float t1c = (nd.n1 != kNoChild) ? box_entry(nd.lo1, nd.hi1) : __builtin_inff();
+        const bool h0 = t0 != __builtin_inff(), h1 = t1c != __builtin_inff();
+        if (!h0 && !h1) continue;
+        // near child first; the far one (if hit) goes on the stack
+        const bool near0 = h0 && (!h1 || t0 <= t1c);
+        if (h0 && h1) {
+          const uint32_t fc = near0 ? nd.c1 : nd.c0, fn = near0 ? nd.n1 : nd.n0;
+          stack_mem[sp++][tid] = (uint16_t)(fn == 0 ? fc : (0x8000u | (e << 1) | (near0 ? 1u : 0u)));
+        }
+        const uint32_t nc = near0 ? nd.c0 : nd.c1, nn = near0 ? nd.n0 : nd.n1;
+        if (nn == 0) {
+          stack_mem[sp++][tid] = (uint16_t)nc;
+        } else {
+          leaf_i = (int)nc;
+          leaf_n = (int)(nc + nn);
+        }
       } else {
-        leaf_i = (int)nc;
-        leaf_n = (int)(nc + nn);
+        // launches whose BVH is not all in LDS: descend to the near child
+        // without the stack (one LDS round trip less before each dependent
+        // node load)
+        // descend: the near child next (an interior one without the stack),
+        // the far one (if hit) on the stack
+        for (;;) {
+          const NodeDev nd = *node_ptr(e);
+          if (COUNT) ++c_nodes;
+          const float t0 = box_entry(nd.lo0, nd.hi0);
+          const float t1c = (nd.n1 != kNoChild) ? box_entry(nd.lo1, nd.hi1) : __builtin_inff();
+          const bool h0 = t0 != __builtin_inff(), h1 = t1c != __builtin_inff();
+          if (!h0 && !h1) break;
+          const bool near0 = h0 && (!h1 || t0 <= t1c);
+          if (h0 && h1) {
+            const uint32_t fc = near0 ? nd.c1 : nd.c0, fn = near0 ? nd.n1 : nd.n0;
+            stack_mem[sp++][tid] = (uint16_t)(fn == 0 ? fc : (0x8000u | (e << 1) | (near0 ? 1u : 0u)));
+          }
+          const uint32_t nc = near0 ? nd.c0 : nd.c1, nn = near0 ? nd.n0 : nd.n1;
+          if (nn == 0) {
+            e = nc;
+            continue;
+          }
+          leaf_i = (int)nc;
+          leaf_n = (int)(nc + nn);
+          break;
+        }
       }
     }
   };
@@ -1301,11 +1330,12 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
     }
     // waves holding long-running pixels get issue priority, the longer the
     // higher: the slowest pixel chains bound the frame time
-    if (__ballot(has_job && job_evals > 4 * kLongJob)) {
+    constexpr uint32_t long_job = DESCEND ? 64u : kLongJob;
+    if (__ballot(has_job && job_evals > 4 * long_job)) {
       __builtin_amdgcn_s_setprio(3);
-    } else if (__ballot(has_job && job_evals > 2 * kLongJob)) {
+    } else if (__ballot(has_job && job_evals > 2 * long_job)) {
       __builtin_amdgcn_s_setprio(2);
-    } else if (__ballot(has_job && job_evals > kLongJob)) {
+    } else if (__ballot(has_job && job_evals > long_job)) {
       __builtin_amdgcn_s_setprio(1);
     } else {
       __builtin_amdgcn_s_setprio(0);
@@ -1337,11 +1367,11 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
 
 #ifndef PR_USER_ESTIMATORS
 
-template <bool COUNT, bool POOL>
+template <bool COUNT, bool POOL, bool DESCEND>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void trace_kernel(
     const ReqDev* __restrict__ reqs, QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  trace_body<COUNT, POOL>(reqs, queue, step_budget, counts);
+  trace_body<COUNT, POOL, DESCEND>(reqs, queue, step_budget, counts);
 }
 
 int device_cu_count() {
@@ -1353,7 +1383,7 @@ int device_cu_count() {
 
 int occupancy_blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<false, false>, kBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<false, false, false>, kBlock, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
@@ -1363,9 +1393,12 @@ int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_job
   (void)total_jobs;
   (void)n_req;
   dim3 grid(cfg.grid_blocks), block(kBlock);
-  // the queue header carries the same compact_pct; it selects the kernel
-  auto k = counts_dev ? (cfg.compact_pct > 0 ? trace_kernel<true, true> : trace_kernel<true, false>)
-                      : (cfg.compact_pct > 0 ? trace_kernel<false, true> : trace_kernel<false, false>);
+  // the queue header carries the same compact_pct; it selects the kernel,
+  // and so does whether the launch's BVH is all staged in LDS (see traverse)
+  auto k = counts_dev ? (cfg.compact_pct > 0 ? trace_kernel<true, true, false> : trace_kernel<true, false, false>)
+                      : (cfg.compact_pct > 0 ? trace_kernel<false, true, false>
+                                             : (cfg.descend ? trace_kernel<false, false, true>
+                                                            : trace_kernel<false, false, false>));
   hipLaunchKernelGGL(k, grid, block, 0, (hipStream_t)stream, reqs_dev, queue_dev, cfg.step_budget, counts_dev);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1380,11 +1413,11 @@ int launch_trace(const ReqDev* reqs_dev, QueueDev* queue_dev, uint32_t total_job
 extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user(
     const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  pr::trace_body<false, false>(reqs, queue, step_budget, counts);
+  pr::trace_body<false, false, false>(reqs, queue, step_budget, counts);
 }
 extern "C" __global__ __launch_bounds__(pr::kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pr_trace_user_count(
     const pr::ReqDev* __restrict__ reqs, pr::QueueDev* __restrict__ queue, int step_budget,
     unsigned long long* __restrict__ counts) {
-  pr::trace_body<true, false>(reqs, queue, step_budget, counts);
+  pr::trace_body<true, false, false>(reqs, queue, step_budget, counts);
 }
 #endif
