@@ -57,6 +57,7 @@ struct pr_scene {
   std::vector<float> world_aabb;         // 6 per instance
   std::vector<pr::HostNode> nodes;       // BVH, children adjacent, breadth-first
   std::vector<pr::NodeDev> dnodes;       // device layout: child boxes in the parent
+  std::vector<pr::Node4Dev> dnodes4;     // four-wide device layout (empty: none)
   std::vector<uint32_t> order;           // leaf slot -> user instance index
   pr::SceneConstsDev consts{};
   bool built = false;
@@ -64,6 +65,7 @@ struct pr_scene {
   int device = -1;
   pr::InstDev* d_insts = nullptr;        // leaf order
   pr::NodeDev* d_nodes = nullptr;
+  pr::Node4Dev* d_nodes4 = nullptr;
   pr::SceneConstsDev* d_consts = nullptr;
   float* d_shade = nullptr;              // leaf order
   uint64_t device_bytes = 0;

@@ -66,6 +66,27 @@ struct alignas(16) NodeDev {
 };
 static_assert(sizeof(NodeDev) == 64, "device BVH node must stay 64 bytes");
 
+// Four-wide BVH node, read by the kernel build for launches whose BVH is not
+// all staged in LDS (half the dependent node loads of the two-wide tree).
+// The boxes of up to four children are stored as 8-bit grid coordinates,
+// child box = org + q * step per axis, on a grid whose cells 1..254 span the
+// node's box, each bound rounded outward and widened by one more cell, so a
+// decoded box (or a slab distance computed from it in float32) always
+// contains the child's box.  ref: kNoRef = no child; bit 31 set = leaf over
+// instance slots [first, first + count) as 1 << 31 | (count - 1) << 24 |
+// first; else the index of the child node.
+constexpr uint32_t kNoRef = 0xffffffffu;
+constexpr uint32_t kMaxNodes4 = 8192;   // stack entries (node, child) fit 16 bits
+struct alignas(16) Node4Dev {
+  float org[3];
+  uint32_t ref0;
+  float step[3];
+  uint32_t ref1;
+  uint8_t q[24];     // child c: lo x, y, z and hi x, y, z at q[6c .. 6c + 5]
+  uint32_t ref2, ref3;
+};
+static_assert(sizeof(Node4Dev) == 64, "four-wide BVH node must stay 64 bytes");
+
 struct alignas(16) SceneConstsDev {
   float light[3];
   float ambient;
@@ -74,7 +95,7 @@ struct alignas(16) SceneConstsDev {
   float background[3];
   uint32_t n_nodes;
   const float* shade;  // per instance slot (BVH leaf order): albedo rgb, reflectivity
-  const void* pad;
+  const Node4Dev* nodes4;   // four-wide BVH (null: the scene has none)
 };
 static_assert(sizeof(SceneConstsDev) == 64, "scene constants");
 

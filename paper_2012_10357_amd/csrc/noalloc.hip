@@ -132,9 +132,13 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
     q.compact_pct = (uint32_t)compact;
     // one scene: every workgroup stages its top BVH levels, first instance
     // records and constants in LDS, as for pr_render
-    q.n_stage_nodes = std::min<uint32_t>((uint32_t)s->dnodes.size(), kLdsNodes);
+    // as in pr_render: the four-wide tree for a BVH not all in LDS, staged
+    // and pointed at by the request record alike
+    const bool descend = compact == 0 && s->dnodes.size() > kLdsNodes && s->d_nodes4 != nullptr;
+    if (descend) r.nodes = (const NodeDev*)s->d_nodes4;
+    q.n_stage_nodes = std::min<uint32_t>((uint32_t)(descend ? s->dnodes4.size() : s->dnodes.size()), kLdsNodes);
     q.n_stage_insts = std::min<uint32_t>(s->consts.n_inst, kLdsInsts);
-    q.stage_nodes = s->d_nodes;
+    q.stage_nodes = descend ? (const NodeDev*)s->d_nodes4 : s->d_nodes;
     q.stage_insts = s->d_insts;
     q.stage_consts = s->d_consts;
 
@@ -144,7 +148,7 @@ extern "C" pr_status pr_render_noalloc(pr_scene* s, const pr_camera* cam, const 
     std::memcpy(&qh, &q, sizeof qh);
     hipLaunchKernelGGL(noalloc_setup, dim3(setup_blocks), dim3(256), 0, (hipStream_t)stream, qh, r, base, zero16);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "noalloc_setup launch");
-    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact, s->dnodes.size() > kLdsNodes};
+    const LaunchCfg cfg{budget_for(s, opts, 0), persistent_grid(total), compact, descend};
     if (launch_trace((const ReqDev*)(base + sizeof(QueueDev)), (QueueDev*)base, total, 1, cfg, nullptr, stream) != 0)
       return set_error(PR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (s->last_use && (e = hipEventRecord(s->last_use, (hipStream_t)stream)) != hipSuccess)

@@ -394,15 +394,29 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
   q.track = track_dev;
   q.done_recs = done_host;
   for (pr_scene* s : scenes) shared = shared && s == scenes[0];
+  // a launch whose two-wide BVH is not all staged in LDS runs the kernel
+  // build that traverses the four-wide BVH (same results), when every scene
+  // of the launch has one
+  bool descend = !user && compact == 0 && counts_dev == nullptr && !(shared && scenes[0]->dnodes.size() <= kLdsNodes);
+  for (pr_scene* s : scenes) descend = descend && s->d_nodes4 != nullptr;
   if (shared) {
     // one scene for the whole launch: every workgroup stages its top BVH
-    // levels, first instance records and constants in LDS
-    q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->dnodes.size(), kLdsNodes);
+    // levels (of the tree its kernel build reads), first instance records
+    // and constants in LDS
+    if (descend) {
+      q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->dnodes4.size(), kLdsNodes);
+      q.stage_nodes = (const NodeDev*)scenes[0]->d_nodes4;
+    } else {
+      q.n_stage_nodes = std::min<uint32_t>((uint32_t)scenes[0]->dnodes.size(), kLdsNodes);
+      q.stage_nodes = scenes[0]->d_nodes;
+    }
     q.n_stage_insts = std::min<uint32_t>(scenes[0]->consts.n_inst, kLdsInsts);
-    q.stage_nodes = scenes[0]->d_nodes;
     q.stage_insts = scenes[0]->d_insts;
     q.stage_consts = scenes[0]->d_consts;
   }
+  // the requests of a four-wide launch point at their scenes' four-wide trees
+  if (descend)
+    for (size_t i = 0; i < table.size(); ++i) table[i].nodes = (const NodeDev*)scenes[i]->d_nodes4;
   std::memcpy(c->host, &q, sizeof q);
   std::memcpy((char*)c->host + sizeof(QueueDev), table.data(), table.size() * sizeof(ReqDev));
   const size_t bytes = sizeof(QueueDev) + reqs.size() * sizeof(ReqDev);
@@ -421,9 +435,6 @@ pr_status launch_prepared(const std::vector<ReqDev>& reqs, const std::vector<pr_
     return user ? launch_trace_user(uk, r0, q0, cf, counts, s)
                 : launch_trace(r0, q0, total_jobs, (uint32_t)reqs.size(), cf, counts, s);
   };
-  // a launch whose BVH is not all staged in LDS runs the kernel build that
-  // descends to near children without the LDS stack (same results)
-  const bool descend = !(shared && scenes[0]->dnodes.size() <= kLdsNodes);
   LaunchCfg cfg{step_budget, grid_for(total_jobs, user ? uk.blocks_per_cu : 0), compact, descend};
   hipError_t e;
   bool graphed = false;

@@ -379,6 +379,123 @@ void build_bvh(pr_scene* s, const pr_bvh_opts& o) {
   s->dnodes = std::move(dn);
 }
 
+// The four-wide device BVH: each node takes the two children of a host
+// interior node and, while it has fewer than four, replaces its interior
+// child of largest surface area by that child's two children.  Nodes are
+// numbered breadth first (the top levels are the ones staged in LDS).
+// Leaves s->dnodes4 empty when the tree would not fit the kernel's limits
+// (node indices, the traversal stack in the worst case, leaf encoding) or a
+// quantized box could not be made to contain its child.
+void build_bvh4(pr_scene* s) {
+  s->dnodes4.clear();
+  const std::vector<HostNode>& hn = s->nodes;
+  if (hn.empty()) return;
+  auto area = [&](uint32_t h) {
+    const double dx = (double)hn[h].hi[0] - hn[h].lo[0], dy = (double)hn[h].hi[1] - hn[h].lo[1],
+                 dz = (double)hn[h].hi[2] - hn[h].lo[2];
+    return dx * dy + dy * dz + dz * dx;
+  };
+  std::vector<uint32_t> queue{0};   // host node of each four-wide node, breadth first
+  std::vector<Node4Dev> out;
+  for (size_t i = 0; i < queue.size(); ++i) {
+    const uint32_t h = queue[i];
+    std::vector<uint32_t> c;
+    if (hn[h].count != 0) {
+      c.push_back(h);   // a single-leaf tree: the root node holds that leaf
+    } else {
+      c = {hn[h].first, hn[h].first + 1};
+      while (c.size() < 4) {
+        int best = -1;
+        for (size_t k = 0; k < c.size(); ++k)
+          if (hn[c[k]].count == 0 && (best < 0 || area(c[k]) > area(c[best]))) best = (int)k;
+        if (best < 0) break;
+        const uint32_t x = c[best];
+        c[best] = hn[x].first;
+        c.insert(c.begin() + best + 1, hn[x].first + 1);
+      }
+    }
+    Node4Dev d{};
+    float plo[3], phi[3];
+    for (int a = 0; a < 3; ++a) {
+      plo[a] = hn[c[0]].lo[a];
+      phi[a] = hn[c[0]].hi[a];
+      for (uint32_t x : c) {
+        plo[a] = std::min(plo[a], hn[x].lo[a]);
+        phi[a] = std::max(phi[a], hn[x].hi[a]);
+      }
+      // cells of at least 2^-20 of the coordinates' magnitude, so that one
+      // cell exceeds the float32 rounding of a decoded bound
+      const float mag = std::max({std::fabs(plo[a]), std::fabs(phi[a]), 1e-30f});
+      float step = std::max((phi[a] - plo[a]) / 253.0f, mag * 9.5367431640625e-7f);
+      d.step[a] = step;
+      d.org[a] = plo[a] - step;
+    }
+    uint32_t refs[4] = {kNoRef, kNoRef, kNoRef, kNoRef};
+    for (size_t k = 0; k < c.size(); ++k) {
+      const HostNode& x = hn[c[k]];
+      for (int a = 0; a < 3; ++a) {
+        double ql = std::floor(((double)x.lo[a] - d.org[a]) / d.step[a]) - 1.0;
+        double qh = std::ceil(((double)x.hi[a] - d.org[a]) / d.step[a]) + 1.0;
+        int lo = (int)std::min(255.0, std::max(0.0, ql)), hi = (int)std::min(255.0, std::max(0.0, qh));
+        // the kernel decodes org + q * step in float32: make sure the box
+        // contains the child's
+        while (lo > 0 && std::fmaf((float)lo, d.step[a], d.org[a]) > x.lo[a]) --lo;
+        while (hi < 255 && std::fmaf((float)hi, d.step[a], d.org[a]) < x.hi[a]) ++hi;
+        if (std::fmaf((float)lo, d.step[a], d.org[a]) > x.lo[a] || std::fmaf((float)hi, d.step[a], d.org[a]) < x.hi[a])
+          return;
+        d.q[6 * k + a] = (uint8_t)lo;
+        d.q[6 * k + 3 + a] = (uint8_t)hi;
+      }
+      if (x.count != 0) {
+        if (x.count > 128 || x.first >= (1u << 24)) return;
+        refs[k] = (1u << 31) | ((x.count - 1) << 24) | x.first;
+      } else {
+        refs[k] = (uint32_t)queue.size();
+        queue.push_back(c[k]);
+      }
+    }
+    d.ref0 = refs[0];
+    d.ref1 = refs[1];
+    d.ref2 = refs[2];
+    d.ref3 = refs[3];
+    out.push_back(d);
+    if (queue.size() > kMaxNodes4) return;
+  }
+  // worst-case stack use: descending into one child pushes its hit siblings
+  std::vector<int> need(out.size(), 0);
+  for (size_t i = out.size(); i-- > 0;) {
+    const uint32_t r[4] = {out[i].ref0, out[i].ref1, out[i].ref2, out[i].ref3};
+    int n = 0, deepest = 0;
+    for (uint32_t x : r)
+      if (x != kNoRef) {
+        ++n;
+        if (!(x >> 31)) deepest = std::max(deepest, need[x]);
+      }
+    need[i] = (n - 1) + deepest;
+  }
+  if (need[0] + 1 > kStackDepth) return;
+  // every instance slot in exactly one leaf, every child index in range
+  std::vector<uint8_t> seen(s->order.size(), 0);
+  for (const Node4Dev& d : out) {
+    const uint32_t r[4] = {d.ref0, d.ref1, d.ref2, d.ref3};
+    for (uint32_t x : r) {
+      if (x == kNoRef) continue;
+      if (x >> 31) {
+        const uint32_t first = x & 0xffffffu, n = ((x >> 24) & 0x7fu) + 1;
+        for (uint32_t k = first; k < first + n; ++k) {
+          if (k >= seen.size() || seen[k]) return;
+          seen[k] = 1;
+        }
+      } else if (x == 0 || x >= out.size()) {
+        return;
+      }
+    }
+  }
+  for (uint8_t v : seen)
+    if (!v) return;
+  s->dnodes4 = std::move(out);
+}
+
 int bvh_depth(const std::vector<HostNode>& nodes, uint32_t ni) {
   if (nodes[ni].count > 0) return 0;
   return 1 + std::max(bvh_depth(nodes, nodes[ni].first), bvh_depth(nodes, nodes[ni].first + 1));
@@ -545,13 +662,16 @@ static bool scene_busy(pr_scene* s) {
 static void free_device(pr_scene* s) {
   if (s->d_insts) (void)hipFree(s->d_insts);
   if (s->d_nodes) (void)hipFree(s->d_nodes);
+  if (s->d_nodes4) (void)hipFree(s->d_nodes4);
   if (s->d_consts) (void)hipFree(s->d_consts);
   if (s->d_shade) (void)hipFree(s->d_shade);
   s->d_insts = nullptr;
   s->d_nodes = nullptr;
+  s->d_nodes4 = nullptr;
   s->d_consts = nullptr;
   s->d_shade = nullptr;
   s->consts.shade = nullptr;
+  s->consts.nodes4 = nullptr;
   s->uploaded = false;
   s->device_bytes = 0;
 }
@@ -569,6 +689,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
     build_bvh(s, o);
     if (bvh_depth(s->nodes, 0) > kMaxDepth)
       return set_error(PR_ERR_UNSUPPORTED, "BVH deeper than %d levels", kMaxDepth);
+    build_bvh4(s);
     s->consts.n_nodes = (uint32_t)s->dnodes.size();
     s->built = true;
     if (o.flags & PR_BVH_HOST_ONLY) return ok();
@@ -594,6 +715,18 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
       free_device(s);
       return hip_fail(e, "hipMalloc(nodes)");
     }
+    const size_t bn4 = s->dnodes4.size() * sizeof(Node4Dev);
+    if (bn4) {
+      if ((e = hipMalloc((void**)&s->d_nodes4, bn4)) != hipSuccess) {
+        free_device(s);
+        return hip_fail(e, "hipMalloc(nodes4)");
+      }
+      if ((e = hipMemcpy(s->d_nodes4, s->dnodes4.data(), bn4, hipMemcpyHostToDevice)) != hipSuccess) {
+        free_device(s);
+        return hip_fail(e, "hipMemcpy(nodes4)");
+      }
+    }
+    s->consts.nodes4 = s->d_nodes4;
     if ((e = hipMalloc((void**)&s->d_consts, sizeof(SceneConstsDev))) != hipSuccess) {
       free_device(s);
       return hip_fail(e, "hipMalloc(consts)");
@@ -611,7 +744,7 @@ pr_status pr_bvh_build(pr_scene* s, const pr_bvh_opts* opts) {
         return hip_fail(e, "hipEventCreate");
     }
     s->device = dev;
-    s->device_bytes = bi + bn + bs + sizeof(SceneConstsDev);
+    s->device_bytes = bi + bn + bn4 + bs + sizeof(SceneConstsDev);
     s->uploaded = true;
     return ok();
   } catch (const std::bad_alloc&) {

@@ -618,16 +618,16 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         return;
       }
       uint32_t e = stack_mem[--sp][tid];
-      if (e & 0x8000u) {
-        // deferred leaf child: read its range from the parent record
-        const NodeDev* pn = node_ptr((e & 0x7fffu) >> 1);
-        const uint32_t c = (e & 1u) ? pn->c1 : pn->c0;
-        const uint32_t n = (e & 1u) ? pn->n1 : pn->n0;
-        leaf_i = (int)c;
-        leaf_n = (int)(c + n);
-        continue;
-      }
       if constexpr (!DESCEND) {
+        if (e & 0x8000u) {
+          // deferred leaf child: read its range from the parent record
+          const NodeDev* pn = node_ptr((e & 0x7fffu) >> 1);
+          const uint32_t c = (e & 1u) ? pn->c1 : pn->c0;
+          const uint32_t n = (e & 1u) ? pn->n1 : pn->n0;
+          leaf_i = (int)c;
+          leaf_n = (int)(c + n);
+          continue;
+        }
         const NodeDev nd = *node_ptr(e);
         if (COUNT) ++c_nodes;
         const float t0 = box_entry(nd.lo0, nd.hi0);
@@ -648,30 +648,69 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
           leaf_n = (int)(nc + nn);
         }
       } else {
-        // launches whose BVH is not all in LDS: descend to the near child
-        // without the stack (one LDS round trip less before each dependent
-        // node load)
-        // descend: the near child next (an interior one without the stack),
-        // the far one (if hit) on the stack
+        // the four-wide tree (launches whose BVH is not all in LDS); stack
+        // entries: a node index, or 0x8000 | node << 2 | child for a
+        // deferred leaf child
+        auto ref_at = [](const Node4Dev& nd, uint32_t c) __attribute__((always_inline)) -> uint32_t {
+          return c == 0u ? nd.ref0 : c == 1u ? nd.ref1 : c == 2u ? nd.ref2 : nd.ref3;
+        };
+        if (e & 0x8000u) {
+          const Node4Dev& pn = *(const Node4Dev*)node_ptr((e & 0x7fffu) >> 2);
+          const uint32_t r = ref_at(pn, e & 3u);
+          leaf_i = (int)(r & 0xffffffu);
+          leaf_n = leaf_i + (int)((r >> 24) & 0x7fu) + 1;
+          continue;
+        }
+        // descend: the nearest child next (an interior one without the
+        // stack), the other hit children on the stack, farthest first
         for (;;) {
-          const NodeDev nd = *node_ptr(e);
-          if (COUNT) ++c_nodes;
-          const float t0 = box_entry(nd.lo0, nd.hi0);
-          const float t1c = (nd.n1 != kNoChild) ? box_entry(nd.lo1, nd.hi1) : __builtin_inff();
-          const bool h0 = t0 != __builtin_inff(), h1 = t1c != __builtin_inff();
-          if (!h0 && !h1) break;
-          const bool near0 = h0 && (!h1 || t0 <= t1c);
-          if (h0 && h1) {
-            const uint32_t fc = near0 ? nd.c1 : nd.c0, fn = near0 ? nd.n1 : nd.n0;
-            stack_mem[sp++][tid] = (uint16_t)(fn == 0 ? fc : (0x8000u | (e << 1) | (near0 ? 1u : 0u)));
+          const Node4Dev nd = *(const Node4Dev*)node_ptr(e);
+          // slab distances of the grid boxes: (org + q step - o) / d
+          const float sx = nd.step[0] * ix, sy = nd.step[1] * iy, sz = nd.step[2] * iz;
+          const float bx = fmaf(nd.org[0], ix, oxi), by = fmaf(nd.org[1], iy, oyi), bz = fmaf(nd.org[2], iz, ozi);
+          float tk[4];
+          uint32_t ik[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const uint8_t* q = nd.q + 6 * c;
+            const float tx0 = fmaf((float)q[0], sx, bx), tx1 = fmaf((float)q[3], sx, bx);
+            const float ty0 = fmaf((float)q[1], sy, by), ty1 = fmaf((float)q[4], sy, by);
+            const float tz0 = fmaf((float)q[2], sz, bz), tz1 = fmaf((float)q[5], sz, bz);
+            const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+            const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
+            tk[c] = (ref_at(nd, (uint32_t)c) != kNoRef && tn <= tf) ? tn : __builtin_inff();
+            ik[c] = (uint32_t)c;
           }
-          const uint32_t nc = near0 ? nd.c0 : nd.c1, nn = near0 ? nd.n0 : nd.n1;
-          if (nn == 0) {
-            e = nc;
+          // order the children by entry distance (missed and absent ones last)
+          auto cswap = [&](int a, int b) __attribute__((always_inline)) {
+            const bool sw = tk[b] < tk[a];
+            const float ta = tk[a], tb = tk[b];
+            const uint32_t ia = ik[a], ib = ik[b];
+            tk[a] = sw ? tb : ta;
+            tk[b] = sw ? ta : tb;
+            ik[a] = sw ? ib : ia;
+            ik[b] = sw ? ia : ib;
+          };
+          cswap(0, 1);
+          cswap(2, 3);
+          cswap(0, 2);
+          cswap(1, 3);
+          cswap(1, 2);
+          if (tk[0] == __builtin_inff()) break;
+#pragma unroll
+          for (int k = 3; k >= 1; --k) {
+            if (tk[k] != __builtin_inff()) {
+              const uint32_t r = ref_at(nd, ik[k]);
+              stack_mem[sp++][tid] = (uint16_t)((r >> 31) ? (0x8000u | (e << 2) | ik[k]) : r);
+            }
+          }
+          const uint32_t r = ref_at(nd, ik[0]);
+          if (!(r >> 31)) {
+            e = r;
             continue;
           }
-          leaf_i = (int)nc;
-          leaf_n = (int)(nc + nn);
+          leaf_i = (int)(r & 0xffffffu);
+          leaf_n = leaf_i + (int)((r >> 24) & 0x7fu) + 1;
           break;
         }
       }
