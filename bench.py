@@ -232,7 +232,8 @@ def bench_batched(P, W, torch, dev, reps=5, compare=True):
             "plain_mrays_s": round(rays / t_plain / 1e6, 2), "plain_ms": round(t_plain * 1e3, 3),
             "speedup": round(t_plain / t_batch, 3),
             "tuned": {"tile": [best.tile_w, best.tile_h], "step_budget": best.step_budget,
-                      "compact_pct": best.compact_pct}}
+                      "regrouping": ("off" if best.compact_pct == P.PR_COMPACT_NEVER
+                                     else f"{best.compact_pct} %")}}
 
 
 def _frame_rate(P, torch, dev, sc, cam, opts, reps=5):
