@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are only meaningful with a visible GPU; leave them selected so
-    # that `-m gpu` on a GPU machine runs them, and fail loudly there if the HIP
+    # that `-m gpu` on a machine with a GPU runs them, and fail loudly there if the HIP
     # library is missing.
     pass
