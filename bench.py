@@ -19,7 +19,8 @@ stream; ``cpu_baseline`` times the FP64 oracle on a bounded pixel sample.
 Sub-objects time C3 (1024 instances, 4 spp) and the batched form (64 requests
 in one persistent launch vs 64 plain launches), each with its own roofline;
 the served form (a 2 s warm-up, then a 30 s open-loop Poisson trace at
-200 req/s and at 100 req/s, server vs FIFO plain launches); and the next-step
+200 req/s and at 100 req/s, server vs FIFO plain launches, and what the GPU
+sustains on that request mix as back-to-back batches); and the next-step
 workloads: the sample scene with its triangle plane, the cut Julia set, the
 Mandelbulb animation, and the teaser with its pac-men as a user hit group.
 ``--only c3|c4`` times just that workload (for profiling).
@@ -436,6 +437,39 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0, warmup_s=2.0):
             "server": served, "fifo_plain": fifo}
 
 
+def bench_served_ceiling(P, W, torch, dev, n_req=480, batch=120):
+    """What the GPU sustains on the served request mix: the first n_req
+    requests of the 200 req/s trace rendered back to back as batches of
+    ``batch`` requests on one stream (no arrivals, no admission), against
+    one plain pr_render per request."""
+    scenes = [P.Scene(s) for s in W.c5_scenes()]
+    reqs = W.c5_requests(n_req, rate_hz=200.0)
+    prim = float(sum(r.opts.width * r.opts.height * r.opts.spp for r in reqs))
+    outs = [torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev) for r in reqs]
+    items = [(scenes[r.scene_index], r.camera, r.opts, o, None, None, i)
+             for i, (r, o) in enumerate(zip(reqs, outs))]
+    batches = [P.make_requests(items[i:i + batch]) for i in range(0, n_req, batch)]
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        P.render_batch(batches[0], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in batches:
+            P.render_batch(b, stream=stream)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for r, o in zip(reqs, outs):
+            P.render(scenes[r.scene_index], r.camera, r.opts, o, stream=stream)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+    for sc_ in scenes:
+        sc_.close()
+    return {"requests": n_req, "batch": batch, "primary_rays": int(prim),
+            "batched_primary_mrays_s": round(prim / t_batch / 1e6, 1),
+            "plain_primary_mrays_s": round(prim / t_plain / 1e6, 1)}
+
+
 def roofline_of(flops, kernel_ms, name, profile=None, **extra):
     """FP32 roofline of one launch; HBM traffic, VALU issue utilisation and
     active-lane fraction from the workload's committed counter profile when
@@ -601,6 +635,8 @@ def main():
         out["served_100hz"] = bench_served(P, W, torch, dev, args.served_seconds, rate_hz=100.0,
                                            warmup_s=args.served_warmup)
         print(f"# served at 100 req/s: {out['served_100hz']}", file=sys.stderr, flush=True)
+        out["served_ceiling"] = bench_served_ceiling(P, W, torch, dev)
+        print(f"# served mix, back-to-back batches: {out['served_ceiling']}", file=sys.stderr, flush=True)
     if not args.no_next:
         out["next"] = bench_next(P, W, torch, dev)
         print(f"# next: {out['next']}", file=sys.stderr, flush=True)
