@@ -94,7 +94,7 @@ typedef struct { float light_pos[3], light_rgb[3], ambient, background[3]; } pr_
 /* Pinhole camera with a vertical field of view in degrees. 40 bytes. */
 typedef struct { float eye[3], target[3], up[3], vfov_deg; } pr_camera;
 
-/* Render options.  64 bytes.
+/* Render options.
  *  seed           jitter seed (64 bit)
  *  spp            samples per pixel, 1..64
  *  jitter         0: pixel centres when spp == 1; otherwise hashed offsets
@@ -112,13 +112,15 @@ typedef struct { float eye[3], target[3], up[3], vfov_deg; } pr_camera;
  *                 screen rectangle covered by the iterative fractals
  *                 (Julia, Mandelbulb) of scenes with at most 256 instances,
  *                 so their long sphere-tracing chains start early
- *  compact_pct    regrouping of live rays: 1..100 = a workgroup pools its
- *                 lanes' sphere-trace queries, sorted by primitive type, and
- *                 re-issues them as full waves whenever fewer than
- *                 compact_pct % of its lanes march or one of its waves
- *                 marches more than one primitive type; PR_COMPACT_NEVER =
- *                 every wave marches its own lanes; 0 = the choice stored for
- *                 the scene's size class (pr_autotune), else the default
+ *  compact_pct    regrouping of live rays: 1..100 = a lane's sphere-trace
+ *                 query waits in a workgroup-wide pool kept per primitive
+ *                 type, and each march burst of a wave claims up to
+ *                 compact_pct % of 64 waiting queries of the type with the
+ *                 most waiting (the higher type on a tie), marches them and
+ *                 returns the unfinished ones to the pool; PR_COMPACT_NEVER =
+ *                 every wave marches its own lanes' queries; 0 = the choice
+ *                 stored for the scene's size class (pr_autotune), else no
+ *                 regrouping
  *  reserved       must be 0
  * The five scheduling fields never change results.  72 bytes. */
 typedef struct {
