@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--no-batch] [--no-served] [--no-c3] [--no-next] [--served-seconds S]
-                    [--only c3|c4] [--compact N]
+                    [--only c3|c4|c5] [--compact N]
 
 One step = one full frame of the teaser workload: 1920x1080, 1 sample per
 pixel, two pac-men + quaternion Julia + power-8 Mandelbulb, 256 march steps,
@@ -23,7 +23,7 @@ the served form (a 2 s warm-up, then a 30 s open-loop Poisson trace at
 sustains on that request mix as back-to-back batches); and the next-step
 workloads: the sample scene with its triangle plane, the cut Julia set, the
 Mandelbulb animation, and the teaser with its pac-men as a user hit group.
-``--only c3|c4`` times just that workload (for profiling).
+``--only c3|c4|c5`` times just that workload (for profiling).
 """
 from __future__ import annotations
 
@@ -131,6 +131,7 @@ KERNEL_SOURCES = ["paper_2012_10357_amd/csrc/trace.hip", "paper_2012_10357_amd/c
 TRAFFIC_PROFILE = "profiles/trace_kernel_teaser_1080p_pmc.md"
 C3_PROFILE = "profiles/trace_kernel_c3_1080p_4spp_pmc.md"
 C4_PROFILE = "profiles/trace_kernel_c4_batch_64req_pmc.md"
+C5_PROFILE = "profiles/trace_kernel_c5_served_mix_pmc.md"
 
 
 def kernel_source_hash() -> str:
@@ -437,37 +438,61 @@ def bench_served(P, W, torch, dev, seconds, rate_hz=200.0, warmup_s=2.0):
             "server": served, "fifo_plain": fifo}
 
 
-def bench_served_ceiling(P, W, torch, dev, n_req=480, batch=120):
+def bench_served_ceiling(P, W, torch, dev, n_req=480, batch=120, counts=True, plain=True):
     """What the GPU sustains on the served request mix: the first n_req
     requests of the 200 req/s trace rendered back to back as batches of
     ``batch`` requests on one stream (no arrivals, no admission), against
-    one plain pr_render per request."""
+    one plain pr_render per request.  With ``counts`` the roofline of a batch
+    launch: algorithmic flops from the instrumented build run on every
+    request (the per-ray work does not depend on the batch), over the batch
+    launches' mean duration from HIP events on the launch stream."""
     scenes = [P.Scene(s) for s in W.c5_scenes()]
     reqs = W.c5_requests(n_req, rate_hz=200.0)
     prim = float(sum(r.opts.width * r.opts.height * r.opts.spp for r in reqs))
     outs = [torch.empty((r.opts.height, r.opts.width, 3), dtype=torch.float32, device=dev) for r in reqs]
+    flops = 0.0
+    rays = None
+    if counts:
+        for r, o in zip(reqs, outs):
+            c = P.render_counts(scenes[r.scene_index], r.camera, r.opts, o)
+            flops += algorithmic_flops(c)
+            rays = c[28:32].astype(np.float64) if rays is None else rays + c[28:32]
     items = [(scenes[r.scene_index], r.camera, r.opts, o, None, None, i)
              for i, (r, o) in enumerate(zip(reqs, outs))]
     batches = [P.make_requests(items[i:i + batch]) for i in range(0, n_req, batch)]
     stream = torch.cuda.Stream(device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in batches]
     with torch.cuda.stream(stream):
         P.render_batch(batches[0], stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for b in batches:
-            P.render_batch(b, stream=stream)
+        for (a, b), bt in zip(ev, batches):
+            a.record(stream)
+            P.render_batch(bt, stream=stream)
+            b.record(stream)
         torch.cuda.synchronize()
         t_batch = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for r, o in zip(reqs, outs):
-            P.render(scenes[r.scene_index], r.camera, r.opts, o, stream=stream)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t0
+        t_plain = None
+        if plain:
+            t0 = time.perf_counter()
+            for r, o in zip(reqs, outs):
+                P.render(scenes[r.scene_index], r.camera, r.opts, o, stream=stream)
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - t0
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     for sc_ in scenes:
         sc_.close()
-    return {"requests": n_req, "batch": batch, "primary_rays": int(prim),
-            "batched_primary_mrays_s": round(prim / t_batch / 1e6, 1),
-            "plain_primary_mrays_s": round(prim / t_plain / 1e6, 1)}
+    out = {"requests": n_req, "batch": batch, "primary_rays": int(prim),
+           "batched_primary_mrays_s": round(prim / t_batch / 1e6, 1)}
+    if t_plain is not None:
+        out["plain_primary_mrays_s"] = round(prim / t_plain / 1e6, 1)
+    if counts:
+        out["rays"] = dict(primary=int(rays[0]), shadow=int(rays[1]), bounce=int(rays[2]),
+                           bounce_shadow=int(rays[3]))
+        out["roofline"] = roofline_of(flops / len(batches), launch_ms,
+                                      f"trace_kernel (one launch of {batch} served requests)",
+                                      profile=C5_PROFILE)
+    return out
 
 
 def roofline_of(flops, kernel_ms, name, profile=None, **extra):
@@ -526,8 +551,9 @@ def main():
                     help="measured length of each open-loop served trace")
     ap.add_argument("--served-warmup", type=float, default=2.0,
                     help="arrivals before this (seconds) are served but not measured")
-    ap.add_argument("--only", choices=["c3", "c4"], default=None,
-                    help="time only this workload (for profiling): C3, or the 64-request batch")
+    ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
+                    help="time only this workload (for profiling): C3, the 64-request batch, or "
+                         "the served request mix as batches")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--budget", type=int, default=0)
     ap.add_argument("--compact", type=int, default=0,
@@ -556,6 +582,10 @@ def main():
         return
     if args.only == "c3":
         print(json.dumps({"c3": bench_c3(P, W, torch, dev, reps=args.steps, compact=args.compact)}), flush=True)
+        return
+    if args.only == "c5":
+        print(json.dumps({"served_ceiling": bench_served_ceiling(P, W, torch, dev, counts=False, plain=False)}),
+              flush=True)
         return
     if args.only == "c4":
         print(json.dumps({"batched": bench_batched(P, W, torch, dev, reps=args.steps, compare=False)}),
