@@ -651,8 +651,11 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
         // the four-wide tree (launches whose BVH is not all in LDS); stack
         // entries: a node index, or 0x8000 | node << 2 | child for a
         // deferred leaf child
+        // child c's reference by selects on its two index bits (an equality
+        // chain on c becomes a divergent branch tree, four per node visit)
         auto ref_at = [](const Node4Dev& nd, uint32_t c) __attribute__((always_inline)) -> uint32_t {
-          return c == 0u ? nd.ref0 : c == 1u ? nd.ref1 : c == 2u ? nd.ref2 : nd.ref3;
+          const uint32_t r01 = (c & 1u) ? nd.ref1 : nd.ref0, r23 = (c & 1u) ? nd.ref3 : nd.ref2;
+          return (c & 2u) ? r23 : r01;
         };
         if (e & 0x8000u) {
           const Node4Dev& pn = *(const Node4Dev*)node_ptr((e & 0x7fffu) >> 2);
