@@ -671,8 +671,10 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
           // slab distances of the grid boxes: (org + q step - o) / d
           const float sx = nd.step[0] * ix, sy = nd.step[1] * iy, sz = nd.step[2] * iz;
           const float bx = fmaf(nd.org[0], ix, oxi), by = fmaf(nd.org[1], iy, oyi), bz = fmaf(nd.org[2], iz, ozi);
-          float tk[4];
-          uint32_t ik[4];
+          // children as sort keys: the entry distance's bits (non-negative
+          // floats order as integers) with the child index in the low two
+          // bits, 0x7f800000 | c for a missed or absent child
+          uint32_t key[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const uint8_t* q = nd.q + 6 * c;
@@ -681,33 +683,29 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
             const float tz0 = fmaf((float)q[2], sz, bz), tz1 = fmaf((float)q[5], sz, bz);
             const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
             const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), limit));
-            tk[c] = (ref_at(nd, (uint32_t)c) != kNoRef && tn <= tf) ? tn : __builtin_inff();
-            ik[c] = (uint32_t)c;
+            const bool hit = ref_at(nd, (uint32_t)c) != kNoRef && tn <= tf;
+            key[c] = (hit ? (__float_as_uint(tn) & 0x7ffffffcu) : 0x7f800000u) | (uint32_t)c;
           }
-          // order the children by entry distance (missed and absent ones last)
+          // nearest first (ties within the two dropped bits by child index)
           auto cswap = [&](int a, int b) __attribute__((always_inline)) {
-            const bool sw = tk[b] < tk[a];
-            const float ta = tk[a], tb = tk[b];
-            const uint32_t ia = ik[a], ib = ik[b];
-            tk[a] = sw ? tb : ta;
-            tk[b] = sw ? ta : tb;
-            ik[a] = sw ? ib : ia;
-            ik[b] = sw ? ia : ib;
+            const uint32_t lo = min(key[a], key[b]), hi = max(key[a], key[b]);
+            key[a] = lo;
+            key[b] = hi;
           };
           cswap(0, 1);
           cswap(2, 3);
           cswap(0, 2);
           cswap(1, 3);
           cswap(1, 2);
-          if (tk[0] == __builtin_inff()) break;
+          if (key[0] >= 0x7f800000u) break;
 #pragma unroll
           for (int k = 3; k >= 1; --k) {
-            if (tk[k] != __builtin_inff()) {
-              const uint32_t r = ref_at(nd, ik[k]);
-              stack_mem[sp++][tid] = (uint16_t)((r >> 31) ? (0x8000u | (e << 2) | ik[k]) : r);
+            if (key[k] < 0x7f800000u) {
+              const uint32_t c = key[k] & 3u, r = ref_at(nd, c);
+              stack_mem[sp++][tid] = (uint16_t)((r >> 31) ? (0x8000u | (e << 2) | c) : r);
             }
           }
-          const uint32_t r = ref_at(nd, ik[0]);
+          const uint32_t r = ref_at(nd, key[0] & 3u);
           if (!(r >> 31)) {
             e = r;
             continue;
