@@ -188,6 +188,42 @@ def test_all_types_scene_with_bounce():
     _check(parity.compare(*flat(*g), orc, "all types + bounce"))
 
 
+def test_stacked_instances_four_wide_tree():
+    """150 identical spheres stacked in one place among 150 scattered spheres
+    and tori: a BVH too large for LDS, so the launch traverses the four-wide
+    tree, whose nodes hold children with equal entry distances.  Against the
+    oracle; a pixel that hits the stack reports its lowest instance id (equal
+    distances, lowest id wins); and bit for bit the image of the regrouping
+    variant, which walks the two-wide tree in another order."""
+    import torch
+    P = require_gpu()
+    rng = np.random.default_rng(77)
+    b = W._SceneBuilder()
+    gs, gt = b.geometry(W.geom_sphere(1.0)), b.geometry(W.geom_torus(1.0, 0.3))
+    m0, m1 = b.material((0.9, 0.3, 0.2)), b.material((0.3, 0.7, 0.9))
+    for _ in range(150):
+        b.instance(gs, m0, W.xform(np.eye(3), 3.0, (0.0, 0.0, 0.0)))
+    for i in range(150):
+        b.instance(gs if i % 2 else gt, m1,
+                   W.xform(W.random_rotation(rng), rng.uniform(0.3, 0.8), rng.uniform(-8.0, 8.0, 3)))
+    scene = b.build(light_pos=(10, 12, -10))
+    cam = W.camera((0, 2, -18), (0, 0, 0), vfov_deg=60)
+    opts = W.RenderOpts(96, 72, spp=1, max_steps=256, eps=1e-4, tmax=100.0, shadows=1)
+    sc = P.Scene(scene)
+    g = gpu_render(P, sc, cam, opts)
+    inst = g[2].reshape(-1)
+    stack = (inst >= 0) & (inst < 150)
+    assert stack.sum() > 200 and (inst[stack] == 0).all(), np.unique(inst[stack])
+    rgb, t, ins = (torch.empty_like(torch.from_numpy(x)).cuda() for x in g)
+    P.render(sc, cam, opts, rgb, t, ins, compact=100)
+    torch.cuda.synchronize()
+    for a, v in zip(g, (rgb, t, ins)):
+        assert np.array_equal(a, v.cpu().numpy(), equal_nan=True)
+    orc = T.render(scene, cam, opts)
+    _check(parity.compare(*flat(*g), orc, "stacked instances, four-wide tree"))
+    sc.close()
+
+
 @pytest.mark.parametrize("eye_z", [3.0, -3.0])
 def test_mandelbulb_down_its_polar_axis(eye_z):
     """A Mandelbulb seen along its polar axis, odd image size: the central
