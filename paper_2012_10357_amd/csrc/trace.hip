@@ -671,9 +671,10 @@ __device__ __forceinline__ void trace_body(const ReqDev* __restrict__ reqs, Queu
           // slab distances of the grid boxes: (org + q step - o) / d
           const float sx = nd.step[0] * ix, sy = nd.step[1] * iy, sz = nd.step[2] * iz;
           const float bx = fmaf(nd.org[0], ix, oxi), by = fmaf(nd.org[1], iy, oyi), bz = fmaf(nd.org[2], iz, ozi);
-          // children as sort keys: the entry distance's bits (non-negative
-          // floats order as integers) with the child index in the low two
-          // bits, 0x7f800000 | c for a missed or absent child
+          // children as sort keys: the entry distance's bits (it is at least
+          // tmin >= 0, so with the sign of a -0 cleared the bits order as the
+          // floats do) with the child index in the low two bits, 0x7f800000 | c
+          // for a missed or absent child
           uint32_t key[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
